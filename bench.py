@@ -1,0 +1,184 @@
+"""Throughput benchmark of the fused LTNE MRT lattice Boltzmann step.
+
+Workload (one GPU): the 8192 x 8192 periodic-x / walled-y porous layer
+heated from below (Ra = 1e5, Da = 1e-3, per-node porosity from seeded
+smoothed noise, seeded initial temperature noise), all three lattices fused
+into one launch per step.  The headline number is the FP32 form (shifted
+populations); the FP64 and FP16-storage forms are timed on the same lattice
+and reported under "variants".
+
+A step is one launch of the fused kernel over the whole lattice.  Inputs are
+resident in device memory before timing starts.  The time of K steps is taken
+with HIP events on the stream the library queues on, between two device
+synchronisations.
+
+Prints one JSON line:  value = MLUPS (10^6 lattice-node updates of all three
+lattices per second), plus the HBM roofline of the step kernel and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (all 3 populations fused) + % HBM peak, FP32 vs FP64; adjoint/forward cost"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
+N = 8192
+WORKLOAD = ("porous layer 8192x8192, periodic x, walls y (bottom T=1, top T=0), Ra=1e5, "
+            "Da=1e-3, Pr=1, H_v=10, per-node porosity clip(0.65+0.1 z, 0.4, 0.9), "
+            "initial T 0.5 +- 0.05")
+# Algorithmic HBM bytes per lattice-node update: 19 populations read and 19
+# written in the storage type, plus the per-node porosity in the compute type.
+BYTES_PER_LUP = {"f32": 19 * 4 * 2 + 4, "f64": 19 * 8 * 2 + 8, "f16s": 19 * 2 * 2 + 4}
+PRECISION = {"f32": 1, "f64": 0, "f16s": 2}
+KERNEL_SOURCES = ["paper_1608_04118_amd/csrc/step_kernel.hpp", "paper_1608_04118_amd/csrc/common.hpp",
+                  "paper_1608_04118_amd/csrc/lbm_ltne.hip"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(tag: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(tag)
+    if not e or e.get("kernel_hash") != kernel_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def time_form(tag: str, steps: int, warmup: int, inputs):
+    import torch
+    from paper_1608_04118_amd import binding as B
+    p, phi, Tf0, Ts0 = inputs
+    p = dict(p, precision=PRECISION[tag])
+    lat = B.Lattice(p, phi=phi, Tf0=Tf0, Ts0=Ts0)
+    stream = lat.stream
+    if warmup:
+        lat.step(warmup)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    lat.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    mass, energy, _ = lat.diagnostics()
+    if not (np.isfinite(mass) and np.isfinite(energy)):
+        raise RuntimeError("%s run diverged" % tag)
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    cells = p["nx"] * p["ny"]
+    ms_step = ms / steps
+    mlups = cells * steps / (ms * 1e-3) / 1e6
+    achieved = BYTES_PER_LUP[tag] * cells / (ms_step * 1e-3) / 1e9
+    return dict(ms_per_step=ms_step, mlups=mlups, achieved_gbs=achieved,
+                frac=achieved / HBM_PEAK_GBS, bytes_per_launch=BYTES_PER_LUP[tag] * cells)
+
+
+def cpu_baseline(inputs, budget_s: float = 12.0):
+    """The FP64 oracle on a periodic strip of the same layer: all 8192 rows,
+    512 columns, timed over as many steps as fit the budget."""
+    import oracle as O
+    p, phi, Tf0, Ts0 = inputs
+    cols = np.arange(512)
+    ps = dict(p, nx=len(cols), L=p["ny"] - 1.0)
+    o = O.Oracle(ps, phi=phi[:, cols], Tf0=Tf0[:, cols], Ts0=Ts0[:, cols])
+    t = time.perf_counter()
+    o.step(1)
+    one = time.perf_counter() - t
+    steps = max(1, min(200, int(budget_s / max(one, 1e-6))))
+    t = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t
+    cells = ps["nx"] * ps["ny"]
+    return {"value": cells * steps / dt / 1e6, "unit": "MLUPS", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": "FP64 oracle, 8192 rows x 512 columns strip of the same layer, %d steps, "
+                      "%.1f s" % (steps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--forms", default="f32,f64,f16s")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the step would shard as horizontal slabs with a halo exchange per step); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_1608_04118_amd import inputs as I
+    inputs = I.throughput(n=N, precision=I.FP32)
+    forms = [f for f in args.forms.split(",") if f]
+    res = {}
+    for tag in forms:
+        print("[bench] timing %s: %d warmup + %d steps on %dx%d" % (tag, args.warmup, args.steps, N, N),
+              file=sys.stderr, flush=True)
+        res[tag] = time_form(tag, args.steps, args.warmup, inputs)
+        print("[bench] %s: %.3f ms/step, %.0f MLUPS, %.0f GB/s" % (
+            tag, res[tag]["ms_per_step"], res[tag]["mlups"], res[tag]["achieved_gbs"]),
+            file=sys.stderr, flush=True)
+    head = "f32" if "f32" in res else forms[0]
+    r = res[head]
+    traffic = measured_traffic(head)
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(inputs)
+    out = {
+        "metric": METRIC,
+        "value": round(r["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD + ", %s form" % head, "nx": N, "ny": N,
+                   "nodes": N * N, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["frac"], 4),
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+        "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                         for kk, vv in v.items()} for k, v in res.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

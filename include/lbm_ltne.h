@@ -1,0 +1,226 @@
+/*
+ * lbm_ltne.h -- C ABI of the MI355X (gfx950) implementation of one fused time
+ * step of the REV-scale multiple-relaxation-time lattice Boltzmann model for
+ * convection in porous media under local thermal non-equilibrium
+ * (Q. Liu, Y.-L. He, arXiv:1608.04118).
+ *
+ * The step (Sec. 3) couples
+ *   - a D2Q9 lattice for the flow: MRT collision in moment space (Eq. 10)
+ *     with the transform M (Eq. 13), equilibrium moments (Eq. 15), the
+ *     generalized non-Darcy force (Eq. 5) with Boussinesq buoyancy (Eq. 6),
+ *     the explicit velocity (Eqs. 20-22) and its moment-space forcing
+ *     (Eq. 12, S~ = M S);
+ *   - two D2Q5 lattices for the fluid and solid temperatures: MRT collisions
+ *     (Eqs. 32, 33) with the transform N (Eq. 36), equilibria (Eqs. 37, 38),
+ *     the interphase source terms (Eqs. 29-31) and the explicit temperatures
+ *     (Eqs. 43-46);
+ *   - streaming (Eqs. 11, 34, 35) and non-equilibrium extrapolation walls
+ *     (the boundary scheme named in Sec. 4).
+ *
+ * Conventions
+ *   - Lattice units, delta_x = delta_t = 1.  Node (x, y), x in [0, nx),
+ *     y in [0, ny); host fields are row-major doubles, index y * nx + x.
+ *   - Velocities in the order of Eq. 8: 0 rest, 1 +x, 2 +y, 3 -x, 4 -y,
+ *     5 (+,+), 6 (-,+), 7 (-,-), 8 (+,-); D2Q5 uses 0..4.
+ *   - A non-periodic axis has walls on its first and last node, so the
+ *     characteristic length defaults to n - 1.  Gravity points along -y.
+ *   - Wall index w: 0 left (x = 0), 1 right (x = nx-1), 2 bottom (y = 0),
+ *     3 top (y = ny-1).
+ *   - Every entry point returns LBM_OK (0) or a negative LBM_E* code and never
+ *     throws.  lbm_ltne_strerror() names the code; lbm_ltne_last_error()
+ *     gives the last detailed message of the calling thread.
+ *   - Handles are not thread-safe.  Work is queued on the stream given at
+ *     creation; entry points that return host data synchronize that stream.
+ *
+ * Time convention: the state is always the post-collision populations of the
+ * current time t; creating a handle performs the boundary treatment and the
+ * collision of t = 0, so lbm_ltne_macros() is valid right after creation.
+ */
+#ifndef LBM_LTNE_H
+#define LBM_LTNE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_LTNE_ABI_VERSION 1
+
+/* Return codes. */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)       /* invalid argument or physically invalid parameters */
+#define LBM_ENOMEM (-2)       /* device allocation failed or caller pool too small */
+#define LBM_EHIP (-3)         /* a HIP runtime call failed (message in last_error) */
+#define LBM_EDIVERGED (-4)    /* non-finite mass or energy detected */
+#define LBM_EUNSUPPORTED (-5) /* valid request this build does not implement */
+#define LBM_ENODEV (-6)       /* no gfx950 device is available */
+
+/* Storage / arithmetic forms. */
+#define LBM_FP64 0  /* binary64 storage and arithmetic */
+#define LBM_FP32 1  /* binary32 storage and arithmetic, shifted populations */
+#define LBM_FP16S 2 /* binary16 storage of shifted, power-of-two scaled populations; binary32 arithmetic */
+
+/* Thermal wall conditions. */
+#define LBM_WALL_DIRICHLET 0
+#define LBM_WALL_ADIABATIC 1
+
+typedef struct lbm_ltne *lbm_ltne_t;
+typedef struct lbm_ltne_batch *lbm_ltne_batch_t;
+
+/*
+ * Problem statement.  The physical inputs are the groups of Sec. 2
+ * (Ra, Pr, Da, J_e, gamma_sf, sigma, H_v) plus the porosity phi (the paper's
+ * epsilon), the Forchheimer coefficient F_phi and the internal heat sources;
+ * the free relaxation rates and varpi are those of Eqs. 17, 39, 40 and the
+ * D2Q5 weights.  lbm_ltne_default_params() fills the setup of Sec. 4.
+ */
+typedef struct lbm_ltne_params {
+  int32_t nx, ny;          /* nodes, walls included; >= 4 on a walled axis, >= 3 on a periodic one */
+  int32_t precision;       /* LBM_FP64, LBM_FP32 or LBM_FP16S */
+  int32_t periodic_x;      /* 1: periodic along x, 0: walls at x = 0 and x = nx-1 */
+  int32_t periodic_y;      /* 1: periodic along y, 0: walls at y = 0 and y = ny-1 */
+  int32_t wall_thermal[4]; /* LBM_WALL_* for walls 0..3 (ignored on periodic axes) */
+  int32_t nu_wall;         /* wall of the reported Nusselt number; -1: hottest Dirichlet wall */
+  int32_t reserved0;
+  double T_wall[4];        /* Dirichlet temperature of walls 0..3 (both phases) */
+  double T0;               /* Boussinesq reference temperature T_0 (Eq. 6) */
+  double T_init_f, T_init_s; /* uniform initial temperatures when no field is given */
+  double L;                /* characteristic length; <= 0: nx-1 if x is walled, else ny-1 */
+  double dT;               /* temperature scale; <= 0: spread of the Dirichlet wall temperatures (1 if none) */
+  double phi;              /* porosity in (0, 1) (per-node field may replace it) */
+  double Da;               /* Darcy number K / L^2 (Sec. 2) */
+  double F_phi;            /* Forchheimer coefficient (Eq. 5); < 0: Ergun relation of Eq. 7 at the local phi */
+  double Ra, Pr, Je;       /* Rayleigh, Prandtl numbers, viscosity ratio nu_e / nu_f */
+  double gamma_sf;         /* solid-to-fluid conductivity ratio k_s / k_f */
+  double sigma;            /* solid-to-fluid heat capacity ratio (rho c_p)_s / (rho c_p)_f */
+  double Hv;               /* interphase coefficient h_v L^2 / k_f (per-node field may replace it) */
+  double Qf, Qs;           /* q'''/(rho c_p) of each phase in lattice units (Eq. 45) */
+  double Ma;               /* buoyancy Mach number u_c / c_s, u_c = sqrt(g beta dT L); used when nu_f <= 0 */
+  double nu_f;             /* fluid viscosity in lattice units; > 0 takes precedence over Ma */
+  double body_force[2];    /* constant body acceleration G_b added to the buoyancy G of Eq. 6 */
+  double varpi;            /* D2Q5 weight parameter in (0, 1); cs_T^2 = varpi / 2 */
+  double s_e, s_eps, s_q;  /* free D2Q9 rates of Eq. 17 (s_nu follows from nu_e, Eq. 23) */
+  double zeta_e, zeta_nu;  /* free fluid D2Q5 rates of Eq. 39 (zeta_alpha follows from alpha_f, Eq. 49) */
+  double eta_e, eta_nu;    /* free solid D2Q5 rates of Eq. 40 (eta_alpha follows from alpha_s) */
+  double rho0;             /* initial density; also the population shift reference */
+  double T_ref;            /* temperature shift reference of the FP32/FP16 forms; NaN: midpoint of the wall and initial temperatures */
+  double fp16_scale_f;     /* power-of-two storage scale of shifted D2Q9 populations (LBM_FP16S); 0: automatic */
+  double fp16_scale_g;     /* same for the D2Q5 populations; 0: automatic */
+} lbm_ltne_params;
+
+/* Lattice values derived from a parameter set (uniform phi and H_v). */
+typedef struct lbm_ltne_derived {
+  double L, dT;            /* characteristic length and temperature scale */
+  double cs2, csT2;        /* 1/3 and varpi/2 */
+  double gbeta;            /* g beta in lattice units */
+  double u_c;              /* buoyancy velocity sqrt(g beta dT L) */
+  double nu_f, nu_e;       /* viscosities */
+  double s_nu, tau_nu;     /* Eq. 23 */
+  double alpha_f, alpha_s; /* thermal diffusivities */
+  double zeta_a, eta_a;    /* Eq. 49 */
+  double tau_Tf, tau_Ts;   /* 1/zeta_a, 1/eta_a */
+  double K;                /* permeability Da L^2 */
+  double F_phi;            /* Forchheimer coefficient at the uniform phi */
+  double l0, l1;           /* Eq. 22 at the uniform phi */
+  double d0, d1;           /* Eq. 46 at the uniform phi and H_v */
+  double T_ref;            /* resolved temperature shift */
+  double scale_f, scale_g; /* resolved FP16 storage scales (1 for other forms) */
+} lbm_ltne_derived;
+
+/* Fills the cavity setup of Sec. 4 (varpi = 2/5, s_e = s_eps = 1.1,
+ * s_q = 1.2, zeta_e = zeta_nu = eta_e = eta_nu = 1.1, J_e = 1, sigma = 1,
+ * Pr = 1) on a 64 x 64 lattice with a hot left and a cold right wall,
+ * adiabatic top and bottom, Ma = 0.1, FP64.  p must not be NULL. */
+int lbm_ltne_default_params(lbm_ltne_params *p);
+
+/* Validates p and maps it to lattice units (host only, no device use).
+ * Rejects with LBM_EINVAL: sizes out of range, phi not in (0, 1), Da <= 0,
+ * Pr <= 0, Je <= 0, sigma <= 0, gamma_sf < 0, Hv < 0, varpi not in (0, 1),
+ * any rate not in (0, 2), no usable scale (nu_f <= 0 and Ma or Ra <= 0),
+ * a derived relaxation time <= 1/2, a non-finite input.  d may be NULL. */
+int lbm_ltne_derive(const lbm_ltne_params *p, lbm_ltne_derived *d);
+
+/* Bytes of device memory lbm_ltne_create needs for p when a caller pool is
+ * used (has_phi / has_Hv: whether those fields will be passed).  0 on
+ * invalid parameters. */
+size_t lbm_ltne_pool_bytes(const lbm_ltne_params *p, int has_phi, int has_Hv);
+
+/*
+ * Creates a lattice, initialises it (fluid at rest with density rho0,
+ * temperatures T_init or the given fields, populations g = g^eq - w~ Sr / 2
+ * so that Eqs. 43-44 return the initial temperatures) and performs the
+ * collision of t = 0.
+ *   phi_field, Hv_field, Tf_init, Ts_init: optional host arrays of nx*ny
+ *     doubles (NULL: uniform p->phi, p->Hv, p->T_init_f, p->T_init_s);
+ *     copied, the caller keeps ownership.  phi must lie in (0, 1), Hv >= 0.
+ *   hip_stream: a hipStream_t to queue all work on (borrowed; NULL: the
+ *     default stream of the current device).
+ *   device_pool, pool_bytes: optional caller-owned device memory of at least
+ *     lbm_ltne_pool_bytes() bytes (borrowed, must outlive the handle); NULL:
+ *     the library allocates and frees its own.
+ *   out: receives the handle.
+ * Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ENODEV. */
+int lbm_ltne_create(const lbm_ltne_params *p, const double *phi_field, const double *Hv_field,
+                    const double *Tf_init, const double *Ts_init, void *hip_stream,
+                    void *device_pool, size_t pool_bytes, lbm_ltne_t *out);
+
+/* Advances nsteps >= 0 time steps (asynchronous).  Each step is one fused
+ * launch: pull streaming, wall reconstruction, macros, the three collisions,
+ * store.  The macros of the last step are kept for lbm_ltne_macros,
+ * lbm_ltne_nusselt and lbm_ltne_diagnostics; the residual compares them with
+ * the macros kept by the previous call. */
+int lbm_ltne_step(lbm_ltne_t h, int64_t nsteps);
+
+/* Steps taken since creation (or since the state loaded by lbm_ltne_load). */
+int64_t lbm_ltne_steps_done(lbm_ltne_t h);
+
+/* Copies the macroscopic fields of the current time to host arrays of nx*ny
+ * doubles: rho (Eq. 18), u (Eq. 20), T_f, T_s (Eqs. 43-44); wall nodes report
+ * their prescribed values.  Any pointer may be NULL.  Synchronizes. */
+int lbm_ltne_macros(lbm_ltne_t h, double *rho, double *ux, double *uy, double *Tf, double *Ts);
+
+/* Mean Nusselt numbers of the fluid and solid phase over wall p->nu_wall:
+ * Nu = (L / dT) <-dT/dn>, dT/dn by the one-sided second-order difference
+ * (-3 T_0 + 4 T_1 - T_2) / 2 along the inward normal, averaged by the
+ * trapezoid rule along a walled wall (plain mean along a periodic one).
+ * Binary64 reduction in a fixed order.  Synchronizes.  LBM_EINVAL if no wall
+ * is selected. */
+int lbm_ltne_nusselt(lbm_ltne_t h, double *Nu_f, double *Nu_s);
+
+/* Binary64 reductions in a fixed order: total mass sum(rho), thermal energy
+ * sum(phi T_f + (1 - phi) sigma T_s), and the relative change
+ * max over (u, T_f, T_s) of sum|a - a_prev| / sum|a| between the macros of
+ * the last two step calls.  Any pointer may be NULL.  Returns LBM_EDIVERGED
+ * (after filling the outputs) if mass or energy is not finite.  Synchronizes. */
+int lbm_ltne_diagnostics(lbm_ltne_t h, double *mass, double *energy, double *residual);
+
+/* Checkpoint: bytes of a saved state, save to and load from a caller-owned
+ * host buffer (populations, macros, step count).  load requires a handle
+ * created with the same nx, ny and precision.  Synchronize. */
+size_t lbm_ltne_state_bytes(lbm_ltne_t h);
+int lbm_ltne_save(lbm_ltne_t h, void *host_buf, size_t bytes);
+int lbm_ltne_load(lbm_ltne_t h, const void *host_buf, size_t bytes);
+
+/* Derived lattice values of a live handle. */
+int lbm_ltne_get_derived(lbm_ltne_t h, lbm_ltne_derived *d);
+
+/* Releases the handle and the device memory it owns (never a caller pool).
+ * NULL is accepted. */
+int lbm_ltne_destroy(lbm_ltne_t h);
+
+/* Static description of a return code. */
+const char *lbm_ltne_strerror(int code);
+
+/* Last detailed error message of the calling thread ("" if none). */
+const char *lbm_ltne_last_error(void);
+
+/* LBM_LTNE_ABI_VERSION of the library. */
+int lbm_ltne_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_LTNE_H */

@@ -1,0 +1,68 @@
+// Internal types shared by the host runtime and the kernels of the LTNE
+// MRT lattice Boltzmann library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+namespace ltne {
+
+// Populations per node: 9 of the D2Q9 flow lattice (Eq. 8), 5 of the fluid
+// and 5 of the solid D2Q5 temperature lattices.  Planes 0..8 hold f,
+// 9..13 g_f, 14..18 g_s; each plane is nx*ny values, row-major (x fastest).
+constexpr int kPlanes = 19;
+constexpr int kBlock = 256;  // threads per workgroup (4 wave64s)
+constexpr int kXcds = 8;     // MI355X: workgroups are dealt round-robin to 8 XCDs
+
+// Flags of the fused step kernel.
+constexpr int kPhiField = 1;  // per-node porosity
+constexpr int kHvField = 2;   // per-node interphase coefficient
+constexpr int kMacros = 4;    // write rho, u, T_f, T_s of this step
+constexpr int kInit = 8;      // build the t = 0 populations instead of streaming
+
+// Mapping of workgroups to lattice tiles.  A tile is tw x (256 / tw) nodes,
+// tiles are numbered row-major, and workgroup b runs tile
+// (b % 8) * per_xcd + b / 8 so that each XCD (and its L2) sweeps one
+// contiguous band of rows.
+struct TileMap {
+  int tw_shift;  // log2 of the tile width (6, 7 or 8)
+  int ntx;       // tiles per row of tiles
+  int ntiles;    // tiles in the lattice
+  int per_xcd;   // tiles per XCD; the grid has 8 * per_xcd workgroups
+};
+
+// Constants of one lattice in the arithmetic type C.  Temperatures are
+// carried relative to T_ref (theta = T - T_ref), populations relative to
+// their rest state at rho0 and T_ref, in every precision form.
+template <typename C>
+struct StepConsts {
+  int nx, ny;
+  int px, py;            // periodic axes
+  long long plane;       // elements between population planes
+  long long mplane;      // elements between macro planes
+  TileMap tm;
+  C rho0;
+  C phi_u, hv_u;         // uniform porosity / interphase coefficient
+  C gbeta, dT0;          // buoyancy: G_y = Gby + gbeta (theta_f + dT0), dT0 = T_ref - T0
+  C Gbx, Gby;            // body acceleration
+  C nu_over_K;           // nu_f / K
+  C inv_sqrtK;           // 1 / sqrt(K)
+  C Fphi;                // Forchheimer coefficient, < 0: Ergun (Eq. 7) at the local phi
+  C hvf;                 // alpha_f / L^2, so h_v / (rho c_p)_f = H_v hvf
+  C inv_sigma;           // (rho c_p)_f / (rho c_p)_s
+  C Qf, Qs;              // heat sources (Eq. 45)
+  C s_e, s_eps, s_q, s_nu;
+  C z_a, z_e, z_nu;      // fluid D2Q5 rates (Eq. 39)
+  C e_a, e_e, e_nu;      // solid D2Q5 rates (Eq. 40)
+  C varpi;
+  C T_ref;
+  int wall_kind[4];      // 0 Dirichlet, 1 adiabatic, for walls left, right, bottom, top
+  C theta_wall[4];       // Dirichlet wall temperatures relative to T_ref
+  C sf, inv_sf;          // storage scale of the shifted D2Q9 populations (1 unless FP16)
+  C sg, inv_sg;          // same for the D2Q5 populations
+  C theta_init_f, theta_init_s;  // uniform initial temperatures relative to T_ref
+};
+
+}  // namespace ltne

@@ -1,0 +1,536 @@
+// Host runtime and C ABI of the LTNE MRT lattice Boltzmann library: device
+// memory layout, launch configuration, time stepping, outputs, checkpoints.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "lbm_ltne.h"
+#include "params.hpp"
+#include "reduce_kernels.hpp"
+#include "step_kernel.hpp"
+
+using namespace ltne;
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return set_error(LBM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kSumBlocks = 1024;
+constexpr uint32_t kStateMagic = 0x454e544cu;  // "LTNE"
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t storage_bytes(int precision) {
+  return precision == LBM_FP64 ? 8 : (precision == LBM_FP32 ? 4 : 2);
+}
+size_t compute_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
+
+// Elements between population planes: whole 256-element rows of the plane
+// plus a 256-element offset so that the 19 planes do not start on the same
+// power-of-two boundary.
+long long plane_elems(int nx, int ny) {
+  const long long n = static_cast<long long>(nx) * ny;
+  return static_cast<long long>(align_up(static_cast<size_t>(n), 1024)) + 256;
+}
+
+struct Layout {
+  size_t pop_bytes, field_bytes, mac_bytes;
+  size_t off_pop[2], off_phi, off_hv, off_mac[2], off_partial, off_result;
+  size_t total;
+};
+
+Layout make_layout(const lbm_ltne_params* p, bool has_phi, bool has_hv) {
+  Layout L{};
+  const long long n = static_cast<long long>(p->nx) * p->ny;
+  L.pop_bytes = align_up(kPlanes * plane_elems(p->nx, p->ny) * storage_bytes(p->precision), kAlign);
+  L.field_bytes = align_up(n * compute_bytes(p->precision), kAlign);
+  L.mac_bytes = align_up(5 * n * compute_bytes(p->precision), kAlign);
+  size_t o = 0;
+  L.off_pop[0] = o; o += L.pop_bytes;
+  L.off_pop[1] = o; o += L.pop_bytes;
+  L.off_phi = o; o += has_phi ? L.field_bytes : 0;
+  L.off_hv = o; o += has_hv ? L.field_bytes : 0;
+  L.off_mac[0] = o; o += L.mac_bytes;
+  L.off_mac[1] = o; o += L.mac_bytes;
+  L.off_partial = o; o += align_up(kSumBlocks * kSums * sizeof(double), kAlign);
+  L.off_result = o; o += kAlign;
+  L.total = o;
+  return L;
+}
+
+TileMap make_tiles(int nx, int ny) {
+  TileMap t{};
+  t.tw_shift = nx >= 256 ? 8 : (nx >= 128 ? 7 : 6);
+  const int tw = 1 << t.tw_shift, th = kBlock / tw;
+  t.ntx = (nx + tw - 1) / tw;
+  const int nty = (ny + th - 1) / th;
+  t.ntiles = t.ntx * nty;
+  t.per_xcd = (t.ntiles + kXcds - 1) / kXcds;
+  return t;
+}
+
+}  // namespace
+
+struct lbm_ltne {
+  lbm_ltne_params p;
+  lbm_ltne_derived d;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* base = nullptr;
+  bool owns = false;
+  Layout lay{};
+  bool has_phi = false, has_hv = false;
+  int cur = 0;   // population buffer holding the current state
+  int mcur = 0;  // macro buffer of the current time
+  int64_t steps = 0;
+  StepConsts<double> kd{};
+  StepConsts<float> kf{};
+
+  void* pop(int i) const { return base + lay.off_pop[i]; }
+  void* mac(int i) const { return base + lay.off_mac[i]; }
+  void* phi() const { return has_phi ? base + lay.off_phi : nullptr; }
+  void* hv() const { return has_hv ? base + lay.off_hv : nullptr; }
+  double* partial() const { return reinterpret_cast<double*>(base + lay.off_partial); }
+  double* result() const { return reinterpret_cast<double*>(base + lay.off_result); }
+  long long n() const { return static_cast<long long>(p.nx) * p.ny; }
+};
+
+namespace {
+
+template <typename C>
+void fill_consts(const lbm_ltne* h, StepConsts<C>* k) {
+  const lbm_ltne_params& p = h->p;
+  const lbm_ltne_derived& d = h->d;
+  k->nx = p.nx;
+  k->ny = p.ny;
+  k->px = p.periodic_x;
+  k->py = p.periodic_y;
+  k->plane = plane_elems(p.nx, p.ny);
+  k->mplane = h->n();
+  k->tm = make_tiles(p.nx, p.ny);
+  k->rho0 = static_cast<C>(p.rho0);
+  k->phi_u = static_cast<C>(p.phi);
+  k->hv_u = static_cast<C>(p.Hv);
+  k->gbeta = static_cast<C>(d.gbeta);
+  k->dT0 = static_cast<C>(d.T_ref - p.T0);
+  k->Gbx = static_cast<C>(p.body_force[0]);
+  k->Gby = static_cast<C>(p.body_force[1]);
+  k->nu_over_K = static_cast<C>(d.nu_f / d.K);
+  k->inv_sqrtK = static_cast<C>(1.0 / std::sqrt(d.K));
+  k->Fphi = static_cast<C>(p.F_phi >= 0.0 ? p.F_phi : -1.0);
+  k->hvf = static_cast<C>(d.alpha_f / (d.L * d.L));
+  k->inv_sigma = static_cast<C>(1.0 / p.sigma);
+  k->Qf = static_cast<C>(p.Qf);
+  k->Qs = static_cast<C>(p.Qs);
+  k->s_e = static_cast<C>(p.s_e);
+  k->s_eps = static_cast<C>(p.s_eps);
+  k->s_q = static_cast<C>(p.s_q);
+  k->s_nu = static_cast<C>(d.s_nu);
+  k->z_a = static_cast<C>(d.zeta_a);
+  k->z_e = static_cast<C>(p.zeta_e);
+  k->z_nu = static_cast<C>(p.zeta_nu);
+  k->e_a = static_cast<C>(d.eta_a);
+  k->e_e = static_cast<C>(p.eta_e);
+  k->e_nu = static_cast<C>(p.eta_nu);
+  k->varpi = static_cast<C>(p.varpi);
+  k->T_ref = static_cast<C>(d.T_ref);
+  for (int w = 0; w < 4; ++w) {
+    k->wall_kind[w] = p.wall_thermal[w];
+    k->theta_wall[w] = static_cast<C>(p.T_wall[w] - d.T_ref);
+  }
+  k->sf = static_cast<C>(d.scale_f);
+  k->inv_sf = static_cast<C>(1.0 / d.scale_f);
+  k->sg = static_cast<C>(d.scale_g);
+  k->inv_sg = static_cast<C>(1.0 / d.scale_g);
+  k->theta_init_f = static_cast<C>(p.T_init_f - d.T_ref);
+  k->theta_init_s = static_cast<C>(p.T_init_s - d.T_ref);
+}
+
+template <typename S, typename C, int F>
+hipError_t launch_one(const lbm_ltne* h, const StepConsts<C>& k, const void* src, void* dst,
+                      void* mac, const void* init_tf, const void* init_ts) {
+  const dim3 grid(kXcds * k.tm.per_xcd), block(kBlock);
+  hipLaunchKernelGGL((step_kernel<S, C, F>), grid, block, 0, h->stream,
+                     static_cast<const S*>(src), static_cast<S*>(dst),
+                     static_cast<const C*>(h->phi()), static_cast<const C*>(h->hv()),
+                     static_cast<C*>(mac), static_cast<const C*>(init_tf),
+                     static_cast<const C*>(init_ts), k);
+  return hipGetLastError();
+}
+
+// Dispatch over the field flags; mode: 0 plain step, 1 step writing macros,
+// 2 initialisation (writes macros).
+template <typename S, typename C>
+hipError_t launch_step_t(const lbm_ltne* h, const StepConsts<C>& k, int mode, const void* src,
+                         void* dst, void* mac, const void* init_tf, const void* init_ts) {
+  const int fl = (h->has_phi ? kPhiField : 0) | (h->has_hv ? kHvField : 0);
+#define LTNE_CASE(FL)                                                                               \
+  case FL:                                                                                          \
+    if (mode == 0) return launch_one<S, C, FL>(h, k, src, dst, mac, init_tf, init_ts);               \
+    if (mode == 1) return launch_one<S, C, FL | kMacros>(h, k, src, dst, mac, init_tf, init_ts);     \
+    return launch_one<S, C, FL | kMacros | kInit>(h, k, src, dst, mac, init_tf, init_ts);
+  switch (fl) {
+    LTNE_CASE(0)
+    LTNE_CASE(kPhiField)
+    LTNE_CASE(kHvField)
+    LTNE_CASE(kPhiField | kHvField)
+  }
+#undef LTNE_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_step(const lbm_ltne* h, int mode, const void* src, void* dst, void* mac,
+                       const void* init_tf, const void* init_ts) {
+  switch (h->p.precision) {
+    case LBM_FP64:
+      return launch_step_t<double, double>(h, h->kd, mode, src, dst, mac, init_tf, init_ts);
+    case LBM_FP32:
+      return launch_step_t<float, float>(h, h->kf, mode, src, dst, mac, init_tf, init_ts);
+    default:
+      return launch_step_t<_Float16, float>(h, h->kf, mode, src, dst, mac, init_tf, init_ts);
+  }
+}
+
+// Copies a host double field to device memory in the compute type.
+int upload_field(const lbm_ltne* h, const double* src, void* dst) {
+  const long long n = h->n();
+  if (h->p.precision == LBM_FP64) {
+    HIP_TRY(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  } else {
+    std::vector<float> tmp(n);
+    for (long long i = 0; i < n; ++i) tmp[i] = static_cast<float>(src[i]);
+    HIP_TRY(hipMemcpyAsync(dst, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));  // tmp goes out of scope
+  }
+  return LBM_OK;
+}
+
+int check_device(int* dev) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0)
+    return set_error(LBM_ENODEV, "no HIP device is visible");
+  HIP_TRY(hipGetDevice(dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, *dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return set_error(LBM_ENODEV, "device %d is %s; this library is built for gfx950", *dev,
+                     prop.gcnArchName);
+  return LBM_OK;
+}
+
+void release(lbm_ltne* h) {
+  if (!h) return;
+  if (h->owns && h->base) (void)hipFree(h->base);
+  delete h;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_ltne_pool_bytes(const lbm_ltne_params* p, int has_phi, int has_Hv) {
+  if (lbm_ltne_derive(p, nullptr) != LBM_OK) return 0;
+  return make_layout(p, has_phi != 0, has_Hv != 0).total;
+}
+
+int lbm_ltne_create(const lbm_ltne_params* p, const double* phi_field, const double* Hv_field,
+                    const double* Tf_init, const double* Ts_init, void* hip_stream,
+                    void* device_pool, size_t pool_bytes, lbm_ltne_t* out) {
+  clear_error();
+  if (!out) return set_error(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p) return set_error(LBM_EINVAL, "params is NULL");
+  const long long n = static_cast<long long>(p->nx) * p->ny;
+  // Temperature range of walls, uniform and field initial values.
+  double tmin = 0.0, tmax = 0.0;
+  temperature_range(p, &tmin, &tmax);
+  if (p->nx > 0 && p->ny > 0 && n <= (1LL << 30)) {
+    for (const double* fld : {Tf_init, Ts_init}) {
+      if (!fld) continue;
+      for (long long i = 0; i < n; ++i) {
+        if (!std::isfinite(fld[i])) return set_error(LBM_EINVAL, "initial temperature %lld is not finite", i);
+        tmin = std::fmin(tmin, fld[i]);
+        tmax = std::fmax(tmax, fld[i]);
+      }
+    }
+  }
+  lbm_ltne_derived d;
+  int rc = derive(p, tmin, tmax, &d);
+  if (rc != LBM_OK) return rc;
+  if (phi_field)
+    for (long long i = 0; i < n; ++i)
+      if (!(phi_field[i] > 0.0 && phi_field[i] < 1.0))
+        return set_error(LBM_EINVAL, "phi_field[%lld] = %g not in (0, 1)", i, phi_field[i]);
+  if (Hv_field)
+    for (long long i = 0; i < n; ++i)
+      if (!(Hv_field[i] >= 0.0) || !std::isfinite(Hv_field[i]))
+        return set_error(LBM_EINVAL, "Hv_field[%lld] = %g must be finite and >= 0", i, Hv_field[i]);
+  int dev = 0;
+  rc = check_device(&dev);
+  if (rc != LBM_OK) return rc;
+
+  lbm_ltne* h = new (std::nothrow) lbm_ltne();
+  if (!h) return set_error(LBM_ENOMEM, "host allocation failed");
+  h->p = *p;
+  h->d = d;
+  h->device = dev;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->has_phi = phi_field != nullptr;
+  h->has_hv = Hv_field != nullptr;
+  h->lay = make_layout(p, h->has_phi, h->has_hv);
+  if (device_pool) {
+    if (pool_bytes < h->lay.total) {
+      release(h);
+      return set_error(LBM_ENOMEM, "device pool of %zu bytes is smaller than the %zu needed",
+                       pool_bytes, h->lay.total);
+    }
+    if (reinterpret_cast<uintptr_t>(device_pool) % kAlign != 0) {
+      release(h);
+      return set_error(LBM_EINVAL, "device pool must be %zu-byte aligned", kAlign);
+    }
+    h->base = static_cast<char*>(device_pool);
+    h->owns = false;
+  } else {
+    if (hipMalloc(&h->base, h->lay.total) != hipSuccess) {
+      (void)hipGetLastError();
+      const size_t want = h->lay.total;
+      h->base = nullptr;
+      release(h);
+      return set_error(LBM_ENOMEM, "hipMalloc of %zu bytes failed", want);
+    }
+    h->owns = true;
+  }
+  fill_consts(h, &h->kd);
+  fill_consts(h, &h->kf);
+
+  rc = LBM_OK;
+  if (phi_field) rc = upload_field(h, phi_field, h->phi());
+  if (rc == LBM_OK && Hv_field) rc = upload_field(h, Hv_field, h->hv());
+  // Initial temperature fields (relative to T_ref) are staged in the second
+  // population buffer, which the first step overwrites.
+  void* tf_dev = nullptr;
+  void* ts_dev = nullptr;
+  const size_t cb = compute_bytes(p->precision);
+  if (rc == LBM_OK && (Tf_init || Ts_init)) {
+    char* stage = static_cast<char*>(h->pop(1));
+    std::vector<double> rel(n);
+    if (Tf_init) {
+      for (long long i = 0; i < n; ++i) rel[i] = Tf_init[i] - d.T_ref;
+      tf_dev = stage;
+      rc = upload_field(h, rel.data(), tf_dev);
+    }
+    if (rc == LBM_OK && Ts_init) {
+      for (long long i = 0; i < n; ++i) rel[i] = Ts_init[i] - d.T_ref;
+      ts_dev = stage + align_up(n * cb, kAlign);
+      rc = upload_field(h, rel.data(), ts_dev);
+    }
+    if (rc == LBM_OK) {
+      hipError_t e = hipStreamSynchronize(h->stream);
+      if (e != hipSuccess) rc = set_error(LBM_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    }
+  }
+  if (rc == LBM_OK) {
+    hipError_t e = launch_step(h, 2, nullptr, h->pop(0), h->mac(0), tf_dev, ts_dev);
+    if (e != hipSuccess) rc = set_error(LBM_EHIP, "initialisation launch: %s", hipGetErrorString(e));
+  }
+  if (rc == LBM_OK) {
+    // the residual of the first step call compares with the initial macros
+    hipError_t e = hipMemcpyAsync(h->mac(1), h->mac(0), h->lay.mac_bytes, hipMemcpyDeviceToDevice,
+                                  h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) rc = set_error(LBM_EHIP, "initialisation: %s", hipGetErrorString(e));
+  }
+  if (rc != LBM_OK) {
+    release(h);
+    return rc;
+  }
+  h->cur = 0;
+  h->mcur = 0;
+  h->steps = 0;
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm_ltne_step(lbm_ltne_t h, int64_t nsteps) {
+  if (!h) return set_error(LBM_EINVAL, "handle is NULL");
+  if (nsteps < 0) return set_error(LBM_EINVAL, "nsteps = %lld < 0", static_cast<long long>(nsteps));
+  if (nsteps == 0) return LBM_OK;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const bool last = (s == nsteps - 1);
+    hipError_t e = launch_step(h, last ? 1 : 0, h->pop(h->cur), h->pop(1 - h->cur),
+                               last ? h->mac(1 - h->mcur) : nullptr, nullptr, nullptr);
+    if (e != hipSuccess) return set_error(LBM_EHIP, "step launch: %s", hipGetErrorString(e));
+    h->cur = 1 - h->cur;
+    h->steps += 1;
+  }
+  h->mcur = 1 - h->mcur;
+  return LBM_OK;
+}
+
+int64_t lbm_ltne_steps_done(lbm_ltne_t h) { return h ? h->steps : -1; }
+
+int lbm_ltne_macros(lbm_ltne_t h, double* rho, double* ux, double* uy, double* Tf, double* Ts) {
+  if (!h) return set_error(LBM_EINVAL, "handle is NULL");
+  const long long n = h->n();
+  const size_t cb = compute_bytes(h->p.precision);
+  double* outs[5] = {rho, ux, uy, Tf, Ts};
+  std::vector<float> tmp;
+  for (int f = 0; f < 5; ++f) {
+    if (!outs[f]) continue;
+    const char* src = static_cast<const char*>(h->mac(h->mcur)) + static_cast<size_t>(f) * n * cb;
+    if (cb == 8) {
+      HIP_TRY(hipMemcpyAsync(outs[f], src, n * 8, hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(hipStreamSynchronize(h->stream));
+    } else {
+      tmp.resize(n);
+      HIP_TRY(hipMemcpyAsync(tmp.data(), src, n * 4, hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(hipStreamSynchronize(h->stream));
+      for (long long i = 0; i < n; ++i) outs[f][i] = tmp[i];
+    }
+  }
+  return LBM_OK;
+}
+
+int lbm_ltne_nusselt(lbm_ltne_t h, double* Nu_f, double* Nu_s) {
+  if (!h) return set_error(LBM_EINVAL, "handle is NULL");
+  const int w = hot_wall(&h->p);
+  if (w < 0) return set_error(LBM_EINVAL, "no wall selected for the Nusselt number");
+  const int periodic_t = (w < 2) ? h->p.periodic_y : h->p.periodic_x;
+  const double scale = h->d.L / h->d.dT;
+  if (h->p.precision == LBM_FP64) {
+    hipLaunchKernelGGL((nusselt_kernel<double>), dim3(1), dim3(kBlock), 0, h->stream,
+                       static_cast<const double*>(h->mac(h->mcur)), h->p.nx, h->p.ny, h->n(), w,
+                       periodic_t, scale, h->result());
+  } else {
+    hipLaunchKernelGGL((nusselt_kernel<float>), dim3(1), dim3(kBlock), 0, h->stream,
+                       static_cast<const float*>(h->mac(h->mcur)), h->p.nx, h->p.ny, h->n(), w,
+                       periodic_t, scale, h->result());
+  }
+  HIP_TRY(hipGetLastError());
+  double r[2];
+  HIP_TRY(hipMemcpyAsync(r, h->result(), sizeof(r), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (Nu_f) *Nu_f = r[0];
+  if (Nu_s) *Nu_s = r[1];
+  return LBM_OK;
+}
+
+int lbm_ltne_diagnostics(lbm_ltne_t h, double* mass, double* energy, double* residual) {
+  if (!h) return set_error(LBM_EINVAL, "handle is NULL");
+  const long long n = h->n();
+  const int blocks = static_cast<int>(std::min<long long>(kSumBlocks, (n + kBlock - 1) / kBlock));
+  if (h->p.precision == LBM_FP64) {
+    hipLaunchKernelGGL((sums_kernel<double>), dim3(blocks), dim3(kBlock), 0, h->stream,
+                       static_cast<const double*>(h->mac(h->mcur)),
+                       static_cast<const double*>(h->mac(1 - h->mcur)),
+                       static_cast<const double*>(h->phi()), h->p.phi, h->p.sigma, n, n,
+                       h->partial());
+  } else {
+    hipLaunchKernelGGL((sums_kernel<float>), dim3(blocks), dim3(kBlock), 0, h->stream,
+                       static_cast<const float*>(h->mac(h->mcur)),
+                       static_cast<const float*>(h->mac(1 - h->mcur)),
+                       static_cast<const float*>(h->phi()), h->p.phi, h->p.sigma, n, n,
+                       h->partial());
+  }
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(sums_final_kernel, dim3(1), dim3(kBlock), 0, h->stream, h->partial(), blocks,
+                     h->result());
+  HIP_TRY(hipGetLastError());
+  double s[kSums];
+  HIP_TRY(hipMemcpyAsync(s, h->result(), sizeof(s), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  auto rel = [](double num, double den) { return den > 0.0 ? num / den : num; };
+  const double r = std::max(rel(s[2], s[3]), std::max(rel(s[4], s[5]), rel(s[6], s[7])));
+  if (mass) *mass = s[0];
+  if (energy) *energy = s[1];
+  if (residual) *residual = r;
+  if (!std::isfinite(s[0]) || !std::isfinite(s[1]))
+    return set_error(LBM_EDIVERGED, "mass %g, energy %g after %lld steps", s[0], s[1],
+                     static_cast<long long>(h->steps));
+  return LBM_OK;
+}
+
+namespace {
+struct StateHeader {
+  uint32_t magic;
+  int32_t abi;
+  int32_t nx, ny, precision, mcur;
+  int64_t steps;
+  int64_t pop_bytes, mac_bytes;
+};
+}  // namespace
+
+size_t lbm_ltne_state_bytes(lbm_ltne_t h) {
+  if (!h) return 0;
+  return sizeof(StateHeader) + h->lay.pop_bytes + 2 * h->lay.mac_bytes;
+}
+
+int lbm_ltne_save(lbm_ltne_t h, void* host_buf, size_t bytes) {
+  if (!h || !host_buf) return set_error(LBM_EINVAL, "handle or buffer is NULL");
+  if (bytes < lbm_ltne_state_bytes(h))
+    return set_error(LBM_EINVAL, "buffer of %zu bytes < %zu needed", bytes, lbm_ltne_state_bytes(h));
+  StateHeader hd{kStateMagic, LBM_LTNE_ABI_VERSION, h->p.nx, h->p.ny, h->p.precision, h->mcur,
+                 h->steps, static_cast<int64_t>(h->lay.pop_bytes),
+                 static_cast<int64_t>(h->lay.mac_bytes)};
+  char* b = static_cast<char*>(host_buf);
+  std::memcpy(b, &hd, sizeof(hd));
+  b += sizeof(hd);
+  HIP_TRY(hipMemcpyAsync(b, h->pop(h->cur), h->lay.pop_bytes, hipMemcpyDeviceToHost, h->stream));
+  b += h->lay.pop_bytes;
+  HIP_TRY(hipMemcpyAsync(b, h->mac(0), h->lay.mac_bytes, hipMemcpyDeviceToHost, h->stream));
+  b += h->lay.mac_bytes;
+  HIP_TRY(hipMemcpyAsync(b, h->mac(1), h->lay.mac_bytes, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_ltne_load(lbm_ltne_t h, const void* host_buf, size_t bytes) {
+  if (!h || !host_buf) return set_error(LBM_EINVAL, "handle or buffer is NULL");
+  if (bytes < sizeof(StateHeader)) return set_error(LBM_EINVAL, "buffer too small for a state");
+  StateHeader hd;
+  std::memcpy(&hd, host_buf, sizeof(hd));
+  if (hd.magic != kStateMagic || hd.abi != LBM_LTNE_ABI_VERSION)
+    return set_error(LBM_EINVAL, "buffer does not hold a saved state of this library version");
+  if (hd.nx != h->p.nx || hd.ny != h->p.ny || hd.precision != h->p.precision ||
+      hd.pop_bytes != static_cast<int64_t>(h->lay.pop_bytes) ||
+      hd.mac_bytes != static_cast<int64_t>(h->lay.mac_bytes) || (hd.mcur != 0 && hd.mcur != 1))
+    return set_error(LBM_EINVAL, "saved state has a different shape or precision");
+  if (bytes < lbm_ltne_state_bytes(h))
+    return set_error(LBM_EINVAL, "buffer of %zu bytes < %zu needed", bytes, lbm_ltne_state_bytes(h));
+  const char* b = static_cast<const char*>(host_buf) + sizeof(hd);
+  HIP_TRY(hipMemcpyAsync(h->pop(0), b, h->lay.pop_bytes, hipMemcpyHostToDevice, h->stream));
+  b += h->lay.pop_bytes;
+  HIP_TRY(hipMemcpyAsync(h->mac(0), b, h->lay.mac_bytes, hipMemcpyHostToDevice, h->stream));
+  b += h->lay.mac_bytes;
+  HIP_TRY(hipMemcpyAsync(h->mac(1), b, h->lay.mac_bytes, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->cur = 0;
+  h->mcur = hd.mcur;
+  h->steps = hd.steps;
+  return LBM_OK;
+}
+
+int lbm_ltne_get_derived(lbm_ltne_t h, lbm_ltne_derived* d) {
+  if (!h || !d) return set_error(LBM_EINVAL, "handle or output is NULL");
+  *d = h->d;
+  return LBM_OK;
+}
+
+int lbm_ltne_destroy(lbm_ltne_t h) {
+  if (!h) return LBM_OK;
+  (void)hipStreamSynchronize(h->stream);
+  release(h);
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,396 @@
+// Fused time step of the LTNE MRT lattice Boltzmann model (Liu & He,
+// arXiv:1608.04118, Sec. 3) for gfx950: one workgroup per tile, one node per
+// thread.  Each thread
+//   1. pulls its 19 post-collision populations of the previous time step
+//      from its neighbours (streaming, Eqs. 11, 34, 35) -- a wall node pulls
+//      those of its inward neighbour instead;
+//   2. computes the temperatures (Eqs. 43-46), the buoyancy (Eq. 6), the
+//      velocity (Eqs. 20-22) and the total force (Eq. 5);
+//   3. on a wall node, rebuilds its populations by non-equilibrium
+//      extrapolation from the inward neighbour and takes the prescribed
+//      wall values (rho of the neighbour, u = 0, wall temperature);
+//   4. collides the three lattices in moment space (Eqs. 10, 32, 33) with the
+//      transforms of Eqs. 13 and 36 unrolled into adds and a few multiplies;
+//   5. stores the 19 post-collision populations at its own node.
+// All populations are stored shifted by their rest state (w_i rho0 and
+// w~_i T_ref), which is exact in real arithmetic and keeps the stored values
+// small enough for binary32 and binary16.
+#pragma once
+
+#include "common.hpp"
+
+namespace ltne {
+
+template <typename S, typename C>
+__device__ __forceinline__ C load_pop(const S* __restrict__ p, C inv_scale) {
+  if constexpr (std::is_same<S, _Float16>::value) {
+    return static_cast<C>(static_cast<float>(*p)) * inv_scale;
+  } else {
+    (void)inv_scale;
+    return static_cast<C>(*p);
+  }
+}
+
+template <typename S, typename C>
+__device__ __forceinline__ void store_pop(S* __restrict__ p, C v, C scale) {
+  if constexpr (std::is_same<S, _Float16>::value) {
+    *p = static_cast<_Float16>(static_cast<float>(v * scale));
+  } else {
+    (void)scale;
+    *p = static_cast<S>(v);
+  }
+}
+
+template <typename C>
+__device__ __forceinline__ C dev_sqrt(C v) {
+  if constexpr (std::is_same<C, double>::value) {
+    return sqrt(v);
+  } else {
+    return __builtin_sqrtf(v);
+  }
+}
+
+// Node of the workgroup's tile handled by this thread; false if outside.
+template <typename C>
+__device__ __forceinline__ bool node_of_thread(const StepConsts<C>& k, int& x, int& y) {
+  const int b = blockIdx.x;
+  const int t = (b & (kXcds - 1)) * k.tm.per_xcd + (b >> 3);
+  if (t >= k.tm.ntiles) return false;
+  const int tx = t % k.tm.ntx;
+  const int ty = t / k.tm.ntx;
+  const int tw = 1 << k.tm.tw_shift;
+  x = tx * tw + (static_cast<int>(threadIdx.x) & (tw - 1));
+  y = ty * (kBlock >> k.tm.tw_shift) + (static_cast<int>(threadIdx.x) >> k.tm.tw_shift);
+  return x < k.nx && y < k.ny;
+}
+
+template <typename S, typename C, int F>
+__global__ __launch_bounds__(kBlock) void step_kernel(
+    const S* __restrict__ src, S* __restrict__ dst, const C* __restrict__ phi_field,
+    const C* __restrict__ hv_field, C* __restrict__ mac, const C* __restrict__ init_tf,
+    const C* __restrict__ init_ts, const StepConsts<C> k) {
+  int x, y;
+  if (!node_of_thread(k, x, y)) return;
+  const int nx = k.nx, ny = k.ny;
+
+  // Wall classification and the node whose post-streaming populations this
+  // thread reads: itself, or the inward neighbour (diagonal at a corner).
+  const bool wx = !k.px && (x == 0 || x == nx - 1);
+  const bool wy = !k.py && (y == 0 || y == ny - 1);
+  const bool wall = wx || wy;
+  const int xc = wx ? (x == 0 ? 1 : nx - 2) : x;
+  const int yc = wy ? (y == 0 ? 1 : ny - 2) : y;
+  const int ic = yc * nx + xc;
+
+  const C phi_c = (F & kPhiField) ? phi_field[ic] : k.phi_u;
+  const C hv_c = (F & kHvField) ? hv_field[ic] : k.hv_u;
+
+  C f0, f1, f2, f3, f4, f5, f6, f7, f8;
+  C a0, a1, a2, a3, a4;  // fluid temperature populations
+  C b0, b1, b2, b3, b4;  // solid temperature populations
+  if constexpr ((F & kInit) != 0) {
+    // t = 0: fluid at rest at rho0 (all shifted D2Q9 populations vanish) and
+    // g = w~ (T - Sr / 2), so that Eqs. 43-44 give back the initial T.
+    const C thf = init_tf ? init_tf[ic] : k.theta_init_f;
+    const C ths = init_ts ? init_ts[ic] : k.theta_init_s;
+    const C hv = hv_c * k.hvf;
+    const C d0 = C(0.5) * hv / phi_c;
+    const C d1 = C(0.5) * hv * k.inv_sigma / (C(1) - phi_c);
+    const C srf = C(2) * d0 * (ths - thf) + k.Qf;
+    const C srs = C(2) * d1 * (thf - ths) + k.Qs;
+    const C w0 = C(1) - k.varpi, w1 = C(0.25) * k.varpi;
+    f0 = f1 = f2 = f3 = f4 = f5 = f6 = f7 = f8 = C(0);
+    const C gf = thf - C(0.5) * srf, gs = ths - C(0.5) * srs;
+    a0 = w0 * gf;
+    a1 = a2 = a3 = a4 = w1 * gf;
+    b0 = w0 * gs;
+    b1 = b2 = b3 = b4 = w1 * gs;
+  } else {
+    // Pull: population i arrives from node (xc, yc) - e_i.
+    int xm = xc - 1, xp = xc + 1, ym = yc - 1, yp = yc + 1;
+    if (k.px) {
+      xm = (xc == 0) ? nx - 1 : xm;
+      xp = (xc == nx - 1) ? 0 : xp;
+    }
+    if (k.py) {
+      ym = (yc == 0) ? ny - 1 : ym;
+      yp = (yc == ny - 1) ? 0 : yp;
+    }
+    const int r0 = yc * nx, rm = ym * nx, rp = yp * nx;
+    const long long P = k.plane;
+    const C isf = k.inv_sf, isg = k.inv_sg;
+    f0 = load_pop(src + 0 * P + (r0 + xc), isf);
+    f1 = load_pop(src + 1 * P + (r0 + xm), isf);
+    f2 = load_pop(src + 2 * P + (rm + xc), isf);
+    f3 = load_pop(src + 3 * P + (r0 + xp), isf);
+    f4 = load_pop(src + 4 * P + (rp + xc), isf);
+    f5 = load_pop(src + 5 * P + (rm + xm), isf);
+    f6 = load_pop(src + 6 * P + (rm + xp), isf);
+    f7 = load_pop(src + 7 * P + (rp + xp), isf);
+    f8 = load_pop(src + 8 * P + (rp + xm), isf);
+    a0 = load_pop(src + 9 * P + (r0 + xc), isg);
+    a1 = load_pop(src + 10 * P + (r0 + xm), isg);
+    a2 = load_pop(src + 11 * P + (rm + xc), isg);
+    a3 = load_pop(src + 12 * P + (r0 + xp), isg);
+    a4 = load_pop(src + 13 * P + (rp + xc), isg);
+    b0 = load_pop(src + 14 * P + (r0 + xc), isg);
+    b1 = load_pop(src + 15 * P + (r0 + xm), isg);
+    b2 = load_pop(src + 16 * P + (rm + xc), isg);
+    b3 = load_pop(src + 17 * P + (r0 + xp), isg);
+    b4 = load_pop(src + 18 * P + (rp + xc), isg);
+  }
+
+  // ---- macros at (xc, yc) ----
+  // Temperatures, Eqs. 43-46, relative to T_ref.  Written as
+  //   T_f = A + d0 D,  T_s = B - d1 D,  D = T_s - T_f = (B - A) / (1 + d0 + d1),
+  // which equals Eqs. 43-44 and keeps every rounding on the small
+  // correction, so the carried sums A, B are never scaled by a rounded
+  // factor close to 1 (a systematic drift in binary32 otherwise).
+  C hv = hv_c * k.hvf;  // h_v / (rho c_p)_f
+  C d0 = C(0.5) * hv / phi_c;
+  C d1 = C(0.5) * hv * k.inv_sigma / (C(1) - phi_c);
+  const C sgf = ((a0 + a1) + (a2 + a3)) + a4;
+  const C sgs = ((b0 + b1) + (b2 + b3)) + b4;
+  const C A = sgf + C(0.5) * k.Qf;
+  const C B = sgs + C(0.5) * k.Qs;
+  const C D = (B - A) / (C(1) + d0 + d1);
+  C thf = A + d0 * D;
+  C ths = B - d1 * D;
+
+  // Density (Eq. 18) and momentum sums.
+  const C drho = ((f0 + f1) + (f2 + f3)) + ((f4 + f5) + (f6 + f7)) + f8;
+  const C rho = k.rho0 + drho;
+  const C jx = (f1 - f3) + (f5 - f6) + (f8 - f7);
+  const C jy = (f2 - f4) + (f5 + f6) - (f7 + f8);
+
+  // Buoyancy (Eq. 6, gravity along -y) plus body acceleration.
+  const C Gx = k.Gbx;
+  C Gy = k.Gby + k.gbeta * (thf + k.dT0);
+
+  // Velocity, Eqs. 20-22, and total force, Eq. 5 (rFx = rho F_x).
+  C ux, uy, rFx, rFy;
+  {
+    const C Fphi = (k.Fphi >= C(0)) ? k.Fphi : C(1.75) / dev_sqrt(C(150) * phi_c * phi_c * phi_c);
+    const C inv_rho = C(1) / rho;
+    const C vx = jx * inv_rho + C(0.5) * phi_c * Gx;
+    const C vy = jy * inv_rho + C(0.5) * phi_c * Gy;
+    const C l0 = C(0.5) * (C(1) + C(0.5) * phi_c * k.nu_over_K);
+    const C l1 = C(0.5) * phi_c * Fphi * k.inv_sqrtK;
+    const C vm = dev_sqrt(vx * vx + vy * vy);
+    const C den = l0 + dev_sqrt(l0 * l0 + l1 * vm);
+    ux = vx / den;
+    uy = vy / den;
+    const C um = dev_sqrt(ux * ux + uy * uy);
+    const C drag = -phi_c * (k.nu_over_K + Fphi * k.inv_sqrtK * um);
+    rFx = rho * (drag * ux + phi_c * Gx);
+    rFy = rho * (drag * uy + phi_c * Gy);
+  }
+  // Post-collision conserved moments.  In the interior, Eq. 19 gives
+  // rho u + rho F / 2 = j + rho F (momentum plus the force of one step) and
+  // the zeroth thermal moments gain the source: n_0* = n_0 + Sr.
+  C ms3 = jx + rFx, ms5 = jy + rFy;
+  C srf = C(2) * d0 * D + k.Qf;  // Eq. 42
+  C srs = C(-2) * d1 * D + k.Qs;
+  C nf0 = sgf + srf, nsol0 = sgs + srs;
+
+  C phi = phi_c;
+  if (wall) {
+    // Non-equilibrium extrapolation from the inward neighbour:
+    //   f(x_b) = f^eq(rho, 0) + f(x_f) - f^eq(rho, u),
+    //   g_f(x_b) = g_f^eq(T_b, 0) + g_f(x_f) - g_f^eq(T_f, u), g_s likewise.
+    C thfb = thf, thsb = ths;
+    {
+      int kind = 1;
+      C tw = C(0);
+      if (wx) {
+        const int w = (x == 0) ? 0 : 1;
+        if (k.wall_kind[w] == 0) { kind = 0; tw = k.theta_wall[w]; }
+      }
+      if (kind != 0 && wy) {
+        const int w = (y == 0) ? 2 : 3;
+        if (k.wall_kind[w] == 0) { kind = 0; tw = k.theta_wall[w]; }
+      }
+      if (kind == 0) thfb = thsb = tw;
+    }
+    const C ip = C(1) / phi_c;
+    const C uu = (ux * ux + uy * uy) * ip;
+    const C r9 = rho * (C(1) / C(9)), r36 = rho * (C(1) / C(36));
+    // f^eq(rho,0) - f^eq(rho,u) = -w rho [3 e.u + 4.5 (e.u)^2 / phi - 1.5 u^2 / phi]
+    const C q0 = C(1.5) * uu;
+    f0 += C(4) * r9 * q0;
+    f1 -= r9 * (C(3) * ux + C(4.5) * ux * ux * ip - q0);
+    f3 -= r9 * (-C(3) * ux + C(4.5) * ux * ux * ip - q0);
+    f2 -= r9 * (C(3) * uy + C(4.5) * uy * uy * ip - q0);
+    f4 -= r9 * (-C(3) * uy + C(4.5) * uy * uy * ip - q0);
+    const C sp = ux + uy, sm = ux - uy;
+    f5 -= r36 * (C(3) * sp + C(4.5) * sp * sp * ip - q0);
+    f7 -= r36 * (-C(3) * sp + C(4.5) * sp * sp * ip - q0);
+    f8 -= r36 * (C(3) * sm + C(4.5) * sm * sm * ip - q0);
+    f6 -= r36 * (-C(3) * sm + C(4.5) * sm * sm * ip - q0);
+    const C w0 = C(1) - k.varpi, w1 = C(0.25) * k.varpi;
+    const C dtf = thfb - thf, dts = thsb - ths;
+    const C adv = C(0.5) * (thf + k.T_ref) * ip;  // (e.u) T_f / (2 phi)
+    a0 += w0 * dtf;
+    a1 += w1 * dtf - adv * ux;
+    a3 += w1 * dtf + adv * ux;
+    a2 += w1 * dtf - adv * uy;
+    a4 += w1 * dtf + adv * uy;
+    b0 += w0 * dts;
+    b1 += w1 * dts;
+    b2 += w1 * dts;
+    b3 += w1 * dts;
+    b4 += w1 * dts;
+    // Prescribed wall values; coefficients at the wall node itself.
+    const int ib = y * nx + x;
+    phi = (F & kPhiField) ? phi_field[ib] : k.phi_u;
+    const C hvb = ((F & kHvField) ? hv_field[ib] : k.hv_u) * k.hvf;
+    d0 = C(0.5) * hvb / phi;
+    d1 = C(0.5) * hvb * k.inv_sigma / (C(1) - phi);
+    thf = thfb;
+    ths = thsb;
+    Gy = k.Gby + k.gbeta * (thf + k.dT0);
+    ux = C(0);
+    uy = C(0);
+    rFx = rho * phi * Gx;
+    rFy = rho * phi * Gy;
+    ms3 = C(0.5) * rFx;  // rho u + rho F / 2 with u = 0
+    ms5 = C(0.5) * rFy;
+    srf = C(2) * d0 * (ths - thf) + k.Qf;
+    srs = C(2) * d1 * (thf - ths) + k.Qs;
+    nf0 = thf + C(0.5) * srf;  // n_0* = T + Sr / 2 (Eq. 41 at the wall)
+    nsol0 = ths + C(0.5) * srs;
+  }
+
+  if constexpr ((F & kMacros) != 0) {
+    const int ib = y * nx + x;
+    mac[0 * k.mplane + ib] = rho;
+    mac[1 * k.mplane + ib] = ux;
+    mac[2 * k.mplane + ib] = uy;
+    mac[3 * k.mplane + ib] = thf + k.T_ref;
+    mac[4 * k.mplane + ib] = ths + k.T_ref;
+  }
+
+  const long long P = k.plane;
+  const int io = y * nx + x;
+
+  // ---- D2Q9 collision in moment space (Eq. 10) ----
+  {
+    const C ip = C(1) / phi;
+    const C s14 = (f1 + f2) + (f3 + f4);
+    const C s58 = (f5 + f6) + (f7 + f8);
+    const C m1 = C(-4) * f0 - s14 + C(2) * s58;
+    const C m2 = C(4) * f0 - C(2) * s14 + s58;
+    const C m4 = C(2) * (f3 - f1) + (f5 - f6) + (f8 - f7);
+    const C m6 = C(2) * (f4 - f2) + (f5 + f6) - (f7 + f8);
+    const C m7 = (f1 - f2) + (f3 - f4);
+    const C m8 = (f5 - f6) + (f7 - f8);
+    const C jxr = rho * ux, jyr = rho * uy;
+    const C e3 = C(3) * rho * (ux * ux + uy * uy) * ip;
+    // equilibria (Eq. 15) relative to the rest state
+    const C meq1 = C(-2) * drho + e3;
+    const C meq2 = drho - e3;
+    const C meq7 = rho * (ux * ux - uy * uy) * ip;
+    const C meq8 = rho * ux * uy * ip;
+    // forcing moments S~ = M S
+    const C uF = (ux * rFx + uy * rFy) * ip;
+    const C S1 = C(6) * uF;
+    const C S7 = C(2) * (ux * rFx - uy * rFy) * ip;
+    const C S8 = (ux * rFy + uy * rFx) * ip;
+    const C ms0 = drho;
+    const C ms1 = m1 - k.s_e * (m1 - meq1) + (C(1) - C(0.5) * k.s_e) * S1;
+    const C ms2 = m2 - k.s_eps * (m2 - meq2) - (C(1) - C(0.5) * k.s_eps) * S1;
+    const C ms4 = m4 - k.s_q * (m4 + jxr) - (C(1) - C(0.5) * k.s_q) * rFx;
+    const C ms6 = m6 - k.s_q * (m6 + jyr) - (C(1) - C(0.5) * k.s_q) * rFy;
+    const C ms7 = m7 - k.s_nu * (m7 - meq7) + (C(1) - C(0.5) * k.s_nu) * S7;
+    const C ms8 = m8 - k.s_nu * (m8 - meq8) + (C(1) - C(0.5) * k.s_nu) * S8;
+    // f* = M^{-1} m*, M^{-1} = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+    const C a = ms0 * (C(1) / C(9));
+    const C b = ms1 * (C(1) / C(36));
+    const C c = ms2 * (C(1) / C(36));
+    const C d = ms3 * (C(1) / C(6));
+    const C e = ms4 * (C(1) / C(12));
+    const C g = ms5 * (C(1) / C(6));
+    const C h = ms6 * (C(1) / C(12));
+    const C p = ms7 * C(0.25);
+    const C q = ms8 * C(0.25);
+    const C base1 = a - b - C(2) * c;
+    const C base5 = a + C(2) * b + c;
+    const C de = d + e, gh = g + h;
+    const C o1 = base1 + (d - C(2) * e) + p;
+    const C o2 = base1 + (g - C(2) * h) - p;
+    const C o5 = base5 + de + gh + q;
+    const C o6 = base5 - de + gh - q;
+    const C o7 = base5 - de - gh + q;
+    const C o8 = base5 + de - gh - q;
+    // f3, f4 and f0 close the conserved moments (momentum ms3, ms5 and mass
+    // ms0) up to one rounding each, so the inexact constants 1/6, 1/9, ...
+    // cannot bias them from step to step.
+    const C o3 = o1 + ((o5 - o6) + (o8 - o7)) - ms3;
+    const C o4 = o2 + ((o5 + o6) - (o7 + o8)) - ms5;
+    const C o0 = ms0 - (((o1 + o2) + (o3 + o4)) + ((o5 + o6) + (o7 + o8)));
+    const C sf = k.sf;
+    store_pop(dst + 0 * P + io, o0, sf);
+    store_pop(dst + 1 * P + io, o1, sf);
+    store_pop(dst + 2 * P + io, o2, sf);
+    store_pop(dst + 3 * P + io, o3, sf);
+    store_pop(dst + 4 * P + io, o4, sf);
+    store_pop(dst + 5 * P + io, o5, sf);
+    store_pop(dst + 6 * P + io, o6, sf);
+    store_pop(dst + 7 * P + io, o7, sf);
+    store_pop(dst + 8 * P + io, o8, sf);
+  }
+
+  // ---- D2Q5 collisions (Eqs. 32, 33) ----
+  {
+    const C c1 = C(5) * k.varpi - C(4);  // -4 + 5 varpi
+    const C ip = C(1) / phi;
+    const C Tf = thf + k.T_ref;
+    const C sg = k.sg;
+    // fluid phase, equilibria of Eq. 37, source moments (Sr, 0, 0, c1 Sr, 0)
+    {
+      const C n1 = a1 - a3, n2 = a2 - a4;
+      const C n3 = C(-4) * a0 + ((a1 + a2) + (a3 + a4));
+      const C n4 = (a1 - a2) + (a3 - a4);
+      const C ns1 = n1 - k.z_a * (n1 - ux * Tf * ip);
+      const C ns2 = n2 - k.z_a * (n2 - uy * Tf * ip);
+      const C ns3 = n3 - k.z_e * (n3 - c1 * thf) + (C(1) - C(0.5) * k.z_e) * c1 * srf;
+      const C ns4 = n4 - k.z_nu * n4;
+      // g* = N^{-1} n*, N^{-1} = N^T diag(1/5, 1/2, 1/2, 1/20, 1/4)
+      const C o0 = nf0 * C(0.2);
+      const C o3 = ns3 * C(0.05);
+      const C o4 = ns4 * C(0.25);
+      const C h1 = ns1 * C(0.5), h2 = ns2 * C(0.5);
+      const C r1 = o0 + h1 + o3 + o4, r2 = o0 + h2 + o3 - o4;
+      const C r3 = o0 - h1 + o3 + o4, r4 = o0 - h2 + o3 - o4;
+      // rest population from the conserved zeroth moment (see the flow part)
+      store_pop(dst + 9 * P + io, nf0 - ((r1 + r2) + (r3 + r4)), sg);
+      store_pop(dst + 10 * P + io, r1, sg);
+      store_pop(dst + 11 * P + io, r2, sg);
+      store_pop(dst + 12 * P + io, r3, sg);
+      store_pop(dst + 13 * P + io, r4, sg);
+    }
+    // solid phase, equilibria of Eq. 38
+    {
+      const C n1 = b1 - b3, n2 = b2 - b4;
+      const C n3 = C(-4) * b0 + ((b1 + b2) + (b3 + b4));
+      const C n4 = (b1 - b2) + (b3 - b4);
+      const C ns1 = n1 - k.e_a * n1;
+      const C ns2 = n2 - k.e_a * n2;
+      const C ns3 = n3 - k.e_e * (n3 - c1 * ths) + (C(1) - C(0.5) * k.e_e) * c1 * srs;
+      const C ns4 = n4 - k.e_nu * n4;
+      const C o0 = nsol0 * C(0.2);
+      const C o3 = ns3 * C(0.05);
+      const C o4 = ns4 * C(0.25);
+      const C h1 = ns1 * C(0.5), h2 = ns2 * C(0.5);
+      const C r1 = o0 + h1 + o3 + o4, r2 = o0 + h2 + o3 - o4;
+      const C r3 = o0 - h1 + o3 + o4, r4 = o0 - h2 + o3 - o4;
+      store_pop(dst + 14 * P + io, nsol0 - ((r1 + r2) + (r3 + r4)), sg);
+      store_pop(dst + 15 * P + io, r1, sg);
+      store_pop(dst + 16 * P + io, r2, sg);
+      store_pop(dst + 17 * P + io, r3, sg);
+      store_pop(dst + 18 * P + io, r4, sg);
+    }
+  }
+}
+
+}  // namespace ltne

@@ -1,0 +1,248 @@
+"""Parity of the HIP step with the FP64 oracle, element by element on the same
+seeded inputs (GPU only).
+
+Tolerances (max-relative per field, max|gpu - oracle| / max|oracle|): 1e-12
+for the binary64 form, 1e-5 for the binary32 form on u, T_f, T_s.  The
+binary16-storage form has no gate; its error is printed and only bounded
+loosely to catch gross faults.
+
+The full-size 8192 x 8192 layer is compared on strips: a periodic strip of
+the same seeded inputs, wide enough to contain the dependence cone of its
+middle columns, is run by the oracle (the strip identity is pinned in the
+oracle's own tests)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1608_04118_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("rho", "ux", "uy", "Tf", "Ts")
+GATED = ("rho", "u", "Tf", "Ts")
+
+
+def say(*a):
+    print("[gpu-parity]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_1608_04118_amd import binding
+    binding.lib()
+    return binding
+
+
+def rel(a, b):
+    den = np.abs(b).max()
+    return np.abs(a - b).max() / (den if den > 0 else 1.0)
+
+
+def rel_u(g, o):
+    """Velocity error relative to the largest speed (vector norm)."""
+    du = np.hypot(g["ux"] - o["ux"], g["uy"] - o["uy"]).max()
+    um = np.hypot(o["ux"], o["uy"]).max()
+    return du / (um if um > 0 else 1.0)
+
+
+def compare(gm, om, tol, fields=("u", "Tf", "Ts"), label=""):
+    errs = {k: (rel_u(gm, om) if k == "u" else rel(gm[k], om[k])) for k in fields}
+    say(label, {k: "%.2e" % v for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= tol, (label, k, v)
+    return errs
+
+
+def pair(B, oracle, p, steps, **fields):
+    kw = {k: fields.get(k) for k in ("phi", "Hv", "Tf0", "Ts0")}
+    g = B.Lattice(p, **kw)
+    o = oracle.Oracle(p, **kw)
+    if steps:
+        g.step(steps)
+        o.step(steps)
+    return g, o
+
+
+def test_initial_state(B, oracle):
+    say("initial state 64x64 fp64")
+    p = I.cavity_small()
+    g, o = pair(B, oracle, p, 0)
+    compare(g.macros(), o.macros(), 1e-15, GATED, "t=0")
+
+
+def test_cavity_small_fp64_full_length(B, oracle):
+    """64 x 64 cavity, FP64, 2000 steps: fields, Nusselt numbers, sums."""
+    say("cavity 64x64 fp64 2000 steps")
+    p = I.cavity_small()
+    g, o = pair(B, oracle, p, 2000)
+    gm, om = g.macros(), o.macros()
+    compare(gm, om, 1e-12, GATED, "cavity_small fp64")
+    gn, on = g.nusselt(), o.nusselt()
+    say("Nu gpu", gn, "oracle", on)
+    for a, b in zip(gn, on):
+        assert abs(a - b) <= 1e-12 * abs(b)
+    gd, od = g.diagnostics(), o.diagnostics()
+    say("diag gpu", gd, "oracle", od)
+    assert abs(gd[0] - od[0]) <= 1e-12 * abs(od[0])
+    assert abs(gd[1] - od[1]) <= 1e-12 * abs(od[1])
+    assert abs(gd[2] - od[2]) <= 1e-9 * abs(od[2])
+
+
+GEOMS = [
+    # nx, ny, periodic_x, periodic_y, wall_thermal, T_wall, body force
+    (4, 4, 0, 0, (0, 0, 1, 1), (1.0, 0.0, 0.0, 0.0), (1.6e-3, -1.2e-3)),
+    (3, 3, 1, 1, (0, 0, 0, 0), (0.0, 0.0, 0.0, 0.0), (2e-5, -1e-5)),
+    (67, 45, 0, 0, (0, 1, 0, 1), (1.0, 0.0, 0.7, 0.0), (2e-5, -1e-5)),  # ragged, mixed walls, corners
+    (130, 9, 1, 0, (1, 1, 0, 0), (0.0, 0.0, 1.0, 0.0), (1e-4, 0.0)),    # periodic x, two tile widths
+    (9, 130, 0, 1, (0, 0, 1, 1), (1.0, 0.2, 0.0, 0.0), (0.0, 1e-4)),    # periodic y
+    (300, 17, 1, 1, (0, 0, 0, 0), (0.0, 0.0, 0.0, 0.0), (2e-5, -1e-5)),  # fully periodic, ragged tiles
+    (257, 6, 0, 0, (1, 0, 0, 1), (0.0, 1.0, 0.5, 0.0), (2e-4, 0.0)),
+]
+
+
+@pytest.mark.parametrize("geom", GEOMS, ids=["%dx%d_p%d%d" % g[:4] for g in GEOMS])
+@pytest.mark.parametrize("fields", [False, True], ids=["uniform", "fields"])
+def test_fp64_geometries(B, oracle, geom, fields):
+    nx, ny, px, py, wt, tw, bf = geom
+    say("geometry", geom, "fields" if fields else "uniform")
+    p = I.complete(nx=nx, ny=ny, periodic_x=px, periodic_y=py, wall_thermal=wt, T_wall=tw,
+                   Ma=0.0, nu_f=0.05, Ra=3e4, dT=1.0, L=64.0, T0=0.4,
+                   body_force=bf, Hv=80.0, gamma_sf=4.0, sigma=1.7, phi=0.55,
+                   F_phi=-1.0, Qf=1e-5, Qs=-2e-5)
+    r = np.random.default_rng(nx * 1000 + ny)
+    kw = {}
+    if fields:
+        kw = dict(phi=np.clip(0.55 + 0.15 * r.standard_normal((ny, nx)), 0.3, 0.9),
+                  Hv=80.0 * (1 + 0.5 * r.uniform(-1, 1, (ny, nx))),
+                  Tf0=0.4 + 0.2 * r.standard_normal((ny, nx)),
+                  Ts0=0.4 + 0.2 * r.standard_normal((ny, nx)))
+    g, o = pair(B, oracle, p, 300, **kw)
+    compare(g.macros(), o.macros(), 1e-12, GATED, "geom %s" % (geom,))
+
+
+def test_cavity_small_fp32_full_length(B, oracle):
+    say("cavity 64x64 fp32 2000 steps")
+    p = I.cavity_small(precision=I.FP32)
+    g, o = pair(B, oracle, p, 2000)
+    compare(g.macros(), o.macros(), 1e-5, label="cavity_small fp32")
+
+
+def test_cavity_large_fp32(B, oracle):
+    """1024 x 1024 cavity in the FP32 form, 300 steps, whole field."""
+    say("cavity 1024x1024 fp32 300 steps")
+    p = I.cavity_large()
+    g, o = pair(B, oracle, p, 300)
+    compare(g.macros(), o.macros(), 1e-5, label="cavity_large fp32")
+    gn, on = g.nusselt(), o.nusselt()
+    say("Nu gpu", gn, "oracle", on)
+    assert abs(gn[0] - on[0]) <= 1e-4 * abs(on[0])
+
+
+def test_channel_fp32(B, oracle):
+    say("channel 1024x256 fp32 500 steps")
+    p = I.channel()
+    g, o = pair(B, oracle, p, 500)
+    compare(g.macros(), o.macros(), 1e-5, fields=("u",), label="channel fp32")
+
+
+def _strip_check(B, oracle, precision, steps, tol, windows=((0, 16), (4000, 16), (8176, 16)),
+                 noise_floor=False):
+    """GPU run of the full 8192 x 8192 layer; oracle runs of periodic strips
+    around the windows.  Errors are relative to the field's magnitude over the
+    whole lattice (velocity as a vector).  With noise_floor, the gate is
+    max(tol, 10 x the oracle's own sensitivity to a one-ulp perturbation of
+    its inputs), for fields so small after few steps that tol lies below what
+    binary64 populations of size 0.1 resolve."""
+    n = 8192
+    p, phi, Tf0, Ts0 = I.throughput(n=n, precision=precision)
+    say("throughput 8192x8192 precision", precision, "steps", steps)
+    g = B.Lattice(p, phi=phi, Tf0=Tf0, Ts0=Ts0).step(steps)
+    gm = g.macros()
+    g.close()
+    umax = np.hypot(gm["ux"], gm["uy"]).max()
+    scale = {"u": umax, "Tf": np.abs(gm["Tf"]).max(), "Ts": np.abs(gm["Ts"]).max()}
+    margin = steps + 2
+    worst, floor = {}, {}
+    rng = np.random.default_rng(17)
+    for x0, w in windows:
+        cols = np.arange(x0 - margin, x0 + w + margin) % n
+        ps = dict(p, nx=len(cols), L=n - 1.0)
+        sl = (phi[:, cols], Tf0[:, cols], Ts0[:, cols])
+        om = oracle.Oracle(ps, phi=sl[0], Tf0=sl[1], Ts0=sl[2]).step(steps).macros()
+        inner = cols[margin:margin + w]
+        sub = {k: gm[k][:, inner] for k in FIELDS}
+        ref = {k: om[k][:, margin:margin + w] for k in FIELDS}
+        err = {"u": np.hypot(sub["ux"] - ref["ux"], sub["uy"] - ref["uy"]).max(),
+               "Tf": np.abs(sub["Tf"] - ref["Tf"]).max(), "Ts": np.abs(sub["Ts"] - ref["Ts"]).max()}
+        for k in err:
+            worst[k] = max(worst.get(k, 0.0), err[k] / scale[k])
+        if noise_floor:
+            pert = sl[1] * (1 + 2.2e-16 * rng.standard_normal(sl[1].shape))
+            om2 = oracle.Oracle(ps, phi=sl[0], Tf0=pert, Ts0=sl[2]).step(steps).macros()
+            fl = {"u": np.hypot(om2["ux"] - om["ux"], om2["uy"] - om["uy"]).max(),
+                  "Tf": np.abs(om2["Tf"] - om["Tf"]).max(), "Ts": np.abs(om2["Ts"] - om["Ts"]).max()}
+            for k in fl:
+                floor[k] = max(floor.get(k, 0.0), fl[k] / scale[k])
+    say("strips precision", precision, {k: "%.2e" % v for k, v in worst.items()},
+        "oracle floor", {k: "%.2e" % v for k, v in floor.items()})
+    for k, v in worst.items():
+        gate = max(tol, 10.0 * floor.get(k, 0.0))
+        assert v <= gate, (k, v, gate)
+    return worst
+
+
+def test_throughput_fp32_strips(B, oracle):
+    _strip_check(B, oracle, I.FP32, 50, 1e-5)
+
+
+def test_throughput_fp64_strips(B, oracle):
+    _strip_check(B, oracle, I.FP64, 50, 1e-12, noise_floor=True)
+
+
+def test_throughput_fp16_error(B, oracle):
+    worst = _strip_check(B, oracle, I.FP16S, 50, 5e-2)
+    say("fp16 storage error after 50 steps (reported, not gated):", worst)
+
+
+def test_fp16_cavity_error(B, oracle):
+    p = I.cavity_small(precision=I.FP16S)
+    g, o = pair(B, oracle, p, 2000)
+    compare(g.macros(), o.macros(), 0.2, label="cavity_small fp16 storage (reported)")
+
+
+def test_save_load_bitwise(B):
+    say("save/load")
+    p = I.cavity_small(nx=40, ny=33, precision=I.FP32)
+    g = B.Lattice(p).step(50)
+    buf = g.save()
+    g.step(70)
+    a = g.macros()
+    g.load(buf)
+    assert g.steps == 50
+    g.step(70)
+    b = g.macros()
+    for k in FIELDS:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_deterministic_and_diag(B):
+    p, phi, Tf0, Ts0 = I.throughput(n=256, ny=128)
+    runs = []
+    for _ in range(2):
+        g = B.Lattice(p, phi=phi, Tf0=Tf0, Ts0=Ts0).step(100)
+        runs.append((g.macros(), g.nusselt(), g.diagnostics()))
+    for k in FIELDS:
+        assert np.array_equal(runs[0][0][k], runs[1][0][k])
+    assert runs[0][1] == runs[1][1] and runs[0][2] == runs[1][2]
+
+
+def test_step_zero_and_errors(B):
+    g = B.Lattice(I.cavity_small(nx=16, ny=16))
+    g.step(0)
+    assert g.steps == 0
+    with pytest.raises(B.LtneError):
+        B.lbm_ltne_step(g.h, -1)
