@@ -98,6 +98,66 @@ def time_form(tag: str, steps: int, warmup: int, inputs):
                 frac=achieved / HBM_PEAK_GBS, bytes_per_launch=BYTES_PER_LUP[tag] * cells)
 
 
+def copy_bandwidth(gib: float = 1.0, reps: int = 5):
+    """Plain device copy of a known size (torch's copy kernel): the
+    reference kernel for the rocprofv3 byte counters, and a practical
+    bandwidth ceiling next to the published peak."""
+    import torch
+    n = int(gib * 2 ** 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_read": n * 4, "bytes_written": n * 4, "ms": ms, "gbs": 2 * n * 4 / ms / 1e6}
+
+
+def ingest_counters(fetch_csv: str, write_csv: str, copy_bytes: int, out_path: str):
+    """Turns two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per
+    dispatch) of `bench.py --forms f32 --copy-check` into HBM bytes per
+    launch of the step kernel, each scaled by the same counter's reading on
+    the plain copy of copy_bytes read and copy_bytes written."""
+    import csv
+
+    def per_kernel(path, counter):
+        rows = list(csv.DictReader(open(path)))
+        vals = {}
+        for r in rows:
+            if r.get("Counter_Name") != counter:
+                continue
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+
+    out = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        vals = per_kernel(path, counter)
+        copy = [v for k, vs in vals.items() if "copy" in k.lower()
+                for v in vs if v * 1024 > 0.25 * copy_bytes]
+        step = [v for k, vs in vals.items()
+                if "step_kernel" in k and ("<float, float, 1>" in k or "IffLi1E" in k) for v in vs]
+        if not copy or not step:
+            raise SystemExit("counters for the copy or the step kernel not found in %s" % path)
+        scale = copy_bytes / (np.median(copy) * 1024.0)
+        out[counter] = {"step_kib_median": float(np.median(step)), "copy_kib_median": float(np.median(copy)),
+                        "scale": float(scale), "step_bytes": float(np.median(step) * 1024.0 * scale)}
+    total = out["FETCH_SIZE"]["step_bytes"] + out["WRITE_SIZE"]["step_bytes"]
+    rec = {"f32": {"kernel_hash": kernel_hash(), "bytes_per_launch": total,
+                   "algorithmic_bytes_per_launch": BYTES_PER_LUP["f32"] * N * N,
+                   "counters": out}}
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def cpu_baseline(inputs, budget_s: float = 12.0):
     """The FP64 oracle on a periodic strip of the same layer: all 8192 rows,
     512 columns, timed over as many steps as fit the budget."""
@@ -127,7 +187,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--forms", default="f32,f64,f16s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-check", action="store_true",
+                    help="also time a plain 1 GiB device copy (reference for the byte counters)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="convert rocprofv3 FETCH_SIZE / WRITE_SIZE runs into profiles/traffic.json")
     args = ap.parse_args()
+    if args.ingest_counters:
+        ingest_counters(args.ingest_counters[0], args.ingest_counters[1], 2 ** 30,
+                        os.path.join(ROOT, "profiles", "traffic.json"))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the step would shard as horizontal slabs with a halo exchange per step); "
@@ -148,6 +216,10 @@ def main():
         print("[bench] %s: %.3f ms/step, %.0f MLUPS, %.0f GB/s" % (
             tag, res[tag]["ms_per_step"], res[tag]["mlups"], res[tag]["achieved_gbs"]),
             file=sys.stderr, flush=True)
+    copy = None
+    if args.copy_check:
+        print("[bench] timing a plain 1 GiB device copy", file=sys.stderr, flush=True)
+        copy = copy_bandwidth()
     head = "f32" if "f32" in res else forms[0]
     r = res[head]
     traffic = measured_traffic(head)
@@ -174,6 +246,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["frac"], 4),
                      "traffic": traffic},
         "cpu_baseline": cpu,
+        "copy_reference": copy,
         "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                          for kk, vv in v.items()} for k, v in res.items()},
     }

@@ -16,14 +16,40 @@ constexpr int kPlanes = 19;
 constexpr int kBlock = 256;  // threads per workgroup (4 wave64s)
 constexpr int kXcds = 8;     // MI355X: workgroups are dealt round-robin to 8 XCDs
 
+// Launch-shape and memory-path choices of the step kernel (compile time).
+#ifndef LTNE_ROWS
+#define LTNE_ROWS 1
+#endif
+#ifndef LTNE_TW_SHIFT_MAX
+#define LTNE_TW_SHIFT_MAX 8
+#endif
+#ifndef LTNE_XCD_REMAP
+#define LTNE_XCD_REMAP 1
+#endif
+#ifndef LTNE_NT_LOAD
+#define LTNE_NT_LOAD 0
+#endif
+#ifndef LTNE_NT_STORE
+#define LTNE_NT_STORE 1
+#endif
+#ifndef LTNE_PLANE_PAD
+#define LTNE_PLANE_PAD 256
+#endif
+constexpr int kRows = LTNE_ROWS;               // nodes per thread along y
+constexpr int kTwShiftMax = LTNE_TW_SHIFT_MAX;  // widest tile: 2^k nodes
+constexpr bool kXcdRemap = LTNE_XCD_REMAP != 0;
+constexpr bool kNtLoad = LTNE_NT_LOAD != 0;
+constexpr bool kNtStore = LTNE_NT_STORE != 0;
+constexpr int kPlanePad = LTNE_PLANE_PAD;      // elements between the end of one plane and the next
+
 // Flags of the fused step kernel.
 constexpr int kPhiField = 1;  // per-node porosity
 constexpr int kHvField = 2;   // per-node interphase coefficient
 constexpr int kMacros = 4;    // write rho, u, T_f, T_s of this step
 constexpr int kInit = 8;      // build the t = 0 populations instead of streaming
 
-// Mapping of workgroups to lattice tiles.  A tile is tw x (256 / tw) nodes,
-// tiles are numbered row-major, and workgroup b runs tile
+// Mapping of workgroups to lattice tiles.  A tile is tw x (kRows 256 / tw)
+// nodes, tiles are numbered row-major, and workgroup b runs tile
 // (b % 8) * per_xcd + b / 8 so that each XCD (and its L2) sweeps one
 // contiguous band of rows.
 struct TileMap {

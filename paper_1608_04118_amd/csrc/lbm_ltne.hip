@@ -35,12 +35,12 @@ size_t storage_bytes(int precision) {
 }
 size_t compute_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
 
-// Elements between population planes: whole 256-element rows of the plane
-// plus a 256-element offset so that the 19 planes do not start on the same
+// Elements between population planes: the plane rounded up to 1024 elements
+// plus kPlanePad, so that the 19 planes do not start on the same
 // power-of-two boundary.
 long long plane_elems(int nx, int ny) {
   const long long n = static_cast<long long>(nx) * ny;
-  return static_cast<long long>(align_up(static_cast<size_t>(n), 1024)) + 256;
+  return static_cast<long long>(align_up(static_cast<size_t>(n), 1024)) + kPlanePad;
 }
 
 struct Layout {
@@ -71,13 +71,16 @@ Layout make_layout(const lbm_ltne_params* p, bool has_phi, bool has_hv) {
 TileMap make_tiles(int nx, int ny) {
   TileMap t{};
   t.tw_shift = nx >= 256 ? 8 : (nx >= 128 ? 7 : 6);
-  const int tw = 1 << t.tw_shift, th = kBlock / tw;
+  if (t.tw_shift > kTwShiftMax) t.tw_shift = kTwShiftMax;
+  const int tw = 1 << t.tw_shift, th = (kBlock / tw) * kRows;
   t.ntx = (nx + tw - 1) / tw;
   const int nty = (ny + th - 1) / th;
   t.ntiles = t.ntx * nty;
   t.per_xcd = (t.ntiles + kXcds - 1) / kXcds;
   return t;
 }
+
+int grid_blocks(const TileMap& t) { return kXcdRemap ? kXcds * t.per_xcd : t.ntiles; }
 
 }  // namespace
 
@@ -159,7 +162,7 @@ void fill_consts(const lbm_ltne* h, StepConsts<C>* k) {
 template <typename S, typename C, int F>
 hipError_t launch_one(const lbm_ltne* h, const StepConsts<C>& k, const void* src, void* dst,
                       void* mac, const void* init_tf, const void* init_ts) {
-  const dim3 grid(kXcds * k.tm.per_xcd), block(kBlock);
+  const dim3 grid(grid_blocks(k.tm)), block(kBlock);
   hipLaunchKernelGGL((step_kernel<S, C, F>), grid, block, 0, h->stream,
                      static_cast<const S*>(src), static_cast<S*>(dst),
                      static_cast<const C*>(h->phi()), static_cast<const C*>(h->hv()),

@@ -21,23 +21,75 @@
 
 namespace ltne {
 
+template <typename S>
+__device__ __forceinline__ S load_raw(const S* __restrict__ p) {
+  if constexpr (kNtLoad) {
+    return __builtin_nontemporal_load(p);
+  } else {
+    return *p;
+  }
+}
+
+// Element i of a plane: a uniform 64-bit plane base plus a 32-bit byte
+// offset (the host keeps every plane below 4 GiB), which maps to the
+// scalar-base + vector-offset form of the global memory instructions.
+template <typename S>
+__device__ __forceinline__ const S* at(const S* __restrict__ base, uint32_t i) {
+  return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + i * static_cast<uint32_t>(sizeof(S)));
+}
+template <typename S>
+__device__ __forceinline__ S* at(S* __restrict__ base, uint32_t i) {
+  return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + i * static_cast<uint32_t>(sizeof(S)));
+}
+
 template <typename S, typename C>
 __device__ __forceinline__ C load_pop(const S* __restrict__ p, C inv_scale) {
   if constexpr (std::is_same<S, _Float16>::value) {
-    return static_cast<C>(static_cast<float>(*p)) * inv_scale;
+    return static_cast<C>(static_cast<float>(load_raw(p))) * inv_scale;
   } else {
     (void)inv_scale;
-    return static_cast<C>(*p);
+    return static_cast<C>(load_raw(p));
+  }
+}
+
+template <typename S>
+__device__ __forceinline__ void store_raw(S* __restrict__ p, S v) {
+  if constexpr (kNtStore) {
+    __builtin_nontemporal_store(v, p);
+  } else {
+    *p = v;
   }
 }
 
 template <typename S, typename C>
 __device__ __forceinline__ void store_pop(S* __restrict__ p, C v, C scale) {
   if constexpr (std::is_same<S, _Float16>::value) {
-    *p = static_cast<_Float16>(static_cast<float>(v * scale));
+    store_raw(p, static_cast<_Float16>(static_cast<float>(v * scale)));
   } else {
     (void)scale;
-    *p = static_cast<S>(v);
+    store_raw(p, static_cast<S>(v));
+  }
+}
+
+// Reciprocal and reciprocal square root: the hardware approximations
+// (v_rcp_f32 / v_rsq_f32, about 1 ulp) in binary32, exact division in
+// binary64.  They only enter coefficients and small corrections, never a
+// rounded factor applied to a conserved sum.
+template <typename C>
+__device__ __forceinline__ C dev_rcp(C v) {
+  if constexpr (std::is_same<C, double>::value) {
+    return 1.0 / v;
+  } else {
+    return __builtin_amdgcn_rcpf(v);
+  }
+}
+
+template <typename C>
+__device__ __forceinline__ C dev_rsqrt(C v) {
+  if constexpr (std::is_same<C, double>::value) {
+    return 1.0 / sqrt(v);
+  } else {
+    return __builtin_amdgcn_rsqf(v);
   }
 }
 
@@ -50,27 +102,12 @@ __device__ __forceinline__ C dev_sqrt(C v) {
   }
 }
 
-// Node of the workgroup's tile handled by this thread; false if outside.
-template <typename C>
-__device__ __forceinline__ bool node_of_thread(const StepConsts<C>& k, int& x, int& y) {
-  const int b = blockIdx.x;
-  const int t = (b & (kXcds - 1)) * k.tm.per_xcd + (b >> 3);
-  if (t >= k.tm.ntiles) return false;
-  const int tx = t % k.tm.ntx;
-  const int ty = t / k.tm.ntx;
-  const int tw = 1 << k.tm.tw_shift;
-  x = tx * tw + (static_cast<int>(threadIdx.x) & (tw - 1));
-  y = ty * (kBlock >> k.tm.tw_shift) + (static_cast<int>(threadIdx.x) >> k.tm.tw_shift);
-  return x < k.nx && y < k.ny;
-}
-
+// One node update: pull, macros, walls, collisions, store.
 template <typename S, typename C, int F>
-__global__ __launch_bounds__(kBlock) void step_kernel(
-    const S* __restrict__ src, S* __restrict__ dst, const C* __restrict__ phi_field,
-    const C* __restrict__ hv_field, C* __restrict__ mac, const C* __restrict__ init_tf,
-    const C* __restrict__ init_ts, const StepConsts<C> k) {
-  int x, y;
-  if (!node_of_thread(k, x, y)) return;
+__device__ __forceinline__ void node_update(
+    const int x, const int y, const S* __restrict__ src, S* __restrict__ dst,
+    const C* __restrict__ phi_field, const C* __restrict__ hv_field, C* __restrict__ mac,
+    const C* __restrict__ init_tf, const C* __restrict__ init_ts, const StepConsts<C>& k) {
   const int nx = k.nx, ny = k.ny;
 
   // Wall classification and the node whose post-streaming populations this
@@ -94,8 +131,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(
     const C thf = init_tf ? init_tf[ic] : k.theta_init_f;
     const C ths = init_ts ? init_ts[ic] : k.theta_init_s;
     const C hv = hv_c * k.hvf;
-    const C d0 = C(0.5) * hv / phi_c;
-    const C d1 = C(0.5) * hv * k.inv_sigma / (C(1) - phi_c);
+    const C d0 = C(0.5) * hv * dev_rcp(phi_c);
+    const C d1 = C(0.5) * hv * k.inv_sigma * dev_rcp(C(1) - phi_c);
     const C srf = C(2) * d0 * (ths - thf) + k.Qf;
     const C srs = C(2) * d1 * (thf - ths) + k.Qs;
     const C w0 = C(1) - k.varpi, w1 = C(0.25) * k.varpi;
@@ -119,25 +156,25 @@ __global__ __launch_bounds__(kBlock) void step_kernel(
     const int r0 = yc * nx, rm = ym * nx, rp = yp * nx;
     const long long P = k.plane;
     const C isf = k.inv_sf, isg = k.inv_sg;
-    f0 = load_pop(src + 0 * P + (r0 + xc), isf);
-    f1 = load_pop(src + 1 * P + (r0 + xm), isf);
-    f2 = load_pop(src + 2 * P + (rm + xc), isf);
-    f3 = load_pop(src + 3 * P + (r0 + xp), isf);
-    f4 = load_pop(src + 4 * P + (rp + xc), isf);
-    f5 = load_pop(src + 5 * P + (rm + xm), isf);
-    f6 = load_pop(src + 6 * P + (rm + xp), isf);
-    f7 = load_pop(src + 7 * P + (rp + xp), isf);
-    f8 = load_pop(src + 8 * P + (rp + xm), isf);
-    a0 = load_pop(src + 9 * P + (r0 + xc), isg);
-    a1 = load_pop(src + 10 * P + (r0 + xm), isg);
-    a2 = load_pop(src + 11 * P + (rm + xc), isg);
-    a3 = load_pop(src + 12 * P + (r0 + xp), isg);
-    a4 = load_pop(src + 13 * P + (rp + xc), isg);
-    b0 = load_pop(src + 14 * P + (r0 + xc), isg);
-    b1 = load_pop(src + 15 * P + (r0 + xm), isg);
-    b2 = load_pop(src + 16 * P + (rm + xc), isg);
-    b3 = load_pop(src + 17 * P + (r0 + xp), isg);
-    b4 = load_pop(src + 18 * P + (rp + xc), isg);
+    f0 = load_pop(at(src + 0 * P, r0 + xc), isf);
+    f1 = load_pop(at(src + 1 * P, r0 + xm), isf);
+    f2 = load_pop(at(src + 2 * P, rm + xc), isf);
+    f3 = load_pop(at(src + 3 * P, r0 + xp), isf);
+    f4 = load_pop(at(src + 4 * P, rp + xc), isf);
+    f5 = load_pop(at(src + 5 * P, rm + xm), isf);
+    f6 = load_pop(at(src + 6 * P, rm + xp), isf);
+    f7 = load_pop(at(src + 7 * P, rp + xp), isf);
+    f8 = load_pop(at(src + 8 * P, rp + xm), isf);
+    a0 = load_pop(at(src + 9 * P, r0 + xc), isg);
+    a1 = load_pop(at(src + 10 * P, r0 + xm), isg);
+    a2 = load_pop(at(src + 11 * P, rm + xc), isg);
+    a3 = load_pop(at(src + 12 * P, r0 + xp), isg);
+    a4 = load_pop(at(src + 13 * P, rp + xc), isg);
+    b0 = load_pop(at(src + 14 * P, r0 + xc), isg);
+    b1 = load_pop(at(src + 15 * P, r0 + xm), isg);
+    b2 = load_pop(at(src + 16 * P, rm + xc), isg);
+    b3 = load_pop(at(src + 17 * P, r0 + xp), isg);
+    b4 = load_pop(at(src + 18 * P, rp + xc), isg);
   }
 
   // ---- macros at (xc, yc) ----
@@ -147,13 +184,14 @@ __global__ __launch_bounds__(kBlock) void step_kernel(
   // correction, so the carried sums A, B are never scaled by a rounded
   // factor close to 1 (a systematic drift in binary32 otherwise).
   C hv = hv_c * k.hvf;  // h_v / (rho c_p)_f
-  C d0 = C(0.5) * hv / phi_c;
-  C d1 = C(0.5) * hv * k.inv_sigma / (C(1) - phi_c);
+  const C rphi_c = dev_rcp(phi_c);
+  C d0 = C(0.5) * hv * rphi_c;
+  C d1 = C(0.5) * hv * k.inv_sigma * dev_rcp(C(1) - phi_c);
   const C sgf = ((a0 + a1) + (a2 + a3)) + a4;
   const C sgs = ((b0 + b1) + (b2 + b3)) + b4;
   const C A = sgf + C(0.5) * k.Qf;
   const C B = sgs + C(0.5) * k.Qs;
-  const C D = (B - A) / (C(1) + d0 + d1);
+  const C D = (B - A) * dev_rcp(C(1) + d0 + d1);
   C thf = A + d0 * D;
   C ths = B - d1 * D;
 
@@ -170,16 +208,17 @@ __global__ __launch_bounds__(kBlock) void step_kernel(
   // Velocity, Eqs. 20-22, and total force, Eq. 5 (rFx = rho F_x).
   C ux, uy, rFx, rFy;
   {
-    const C Fphi = (k.Fphi >= C(0)) ? k.Fphi : C(1.75) / dev_sqrt(C(150) * phi_c * phi_c * phi_c);
-    const C inv_rho = C(1) / rho;
+    const C Fphi = (k.Fphi >= C(0)) ? k.Fphi : C(1.75) * dev_rsqrt(C(150) * phi_c * phi_c * phi_c);
+    const C inv_rho = dev_rcp(rho);
     const C vx = jx * inv_rho + C(0.5) * phi_c * Gx;
     const C vy = jy * inv_rho + C(0.5) * phi_c * Gy;
     const C l0 = C(0.5) * (C(1) + C(0.5) * phi_c * k.nu_over_K);
     const C l1 = C(0.5) * phi_c * Fphi * k.inv_sqrtK;
     const C vm = dev_sqrt(vx * vx + vy * vy);
     const C den = l0 + dev_sqrt(l0 * l0 + l1 * vm);
-    ux = vx / den;
-    uy = vy / den;
+    const C rden = dev_rcp(den);
+    ux = vx * rden;
+    uy = vy * rden;
     const C um = dev_sqrt(ux * ux + uy * uy);
     const C drag = -phi_c * (k.nu_over_K + Fphi * k.inv_sqrtK * um);
     rFx = rho * (drag * ux + phi_c * Gx);
@@ -194,6 +233,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(
   C nf0 = sgf + srf, nsol0 = sgs + srs;
 
   C phi = phi_c;
+  C rphi = rphi_c;
   if (wall) {
     // Non-equilibrium extrapolation from the inward neighbour:
     //   f(x_b) = f^eq(rho, 0) + f(x_f) - f^eq(rho, u),
@@ -212,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(
       }
       if (kind == 0) thfb = thsb = tw;
     }
-    const C ip = C(1) / phi_c;
+    const C ip = rphi_c;
     const C uu = (ux * ux + uy * uy) * ip;
     const C r9 = rho * (C(1) / C(9)), r36 = rho * (C(1) / C(36));
     // f^eq(rho,0) - f^eq(rho,u) = -w rho [3 e.u + 4.5 (e.u)^2 / phi - 1.5 u^2 / phi]
@@ -243,9 +283,10 @@ __global__ __launch_bounds__(kBlock) void step_kernel(
     // Prescribed wall values; coefficients at the wall node itself.
     const int ib = y * nx + x;
     phi = (F & kPhiField) ? phi_field[ib] : k.phi_u;
+    rphi = dev_rcp(phi);
     const C hvb = ((F & kHvField) ? hv_field[ib] : k.hv_u) * k.hvf;
-    d0 = C(0.5) * hvb / phi;
-    d1 = C(0.5) * hvb * k.inv_sigma / (C(1) - phi);
+    d0 = C(0.5) * hvb * rphi;
+    d1 = C(0.5) * hvb * k.inv_sigma * dev_rcp(C(1) - phi);
     thf = thfb;
     ths = thsb;
     Gy = k.Gby + k.gbeta * (thf + k.dT0);
@@ -275,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(
 
   // ---- D2Q9 collision in moment space (Eq. 10) ----
   {
-    const C ip = C(1) / phi;
+    const C ip = rphi;
     const C s14 = (f1 + f2) + (f3 + f4);
     const C s58 = (f5 + f6) + (f7 + f8);
     const C m1 = C(-4) * f0 - s14 + C(2) * s58;
@@ -329,21 +370,21 @@ __global__ __launch_bounds__(kBlock) void step_kernel(
     const C o4 = o2 + ((o5 + o6) - (o7 + o8)) - ms5;
     const C o0 = ms0 - (((o1 + o2) + (o3 + o4)) + ((o5 + o6) + (o7 + o8)));
     const C sf = k.sf;
-    store_pop(dst + 0 * P + io, o0, sf);
-    store_pop(dst + 1 * P + io, o1, sf);
-    store_pop(dst + 2 * P + io, o2, sf);
-    store_pop(dst + 3 * P + io, o3, sf);
-    store_pop(dst + 4 * P + io, o4, sf);
-    store_pop(dst + 5 * P + io, o5, sf);
-    store_pop(dst + 6 * P + io, o6, sf);
-    store_pop(dst + 7 * P + io, o7, sf);
-    store_pop(dst + 8 * P + io, o8, sf);
+    store_pop(at(dst + 0 * P, io), o0, sf);
+    store_pop(at(dst + 1 * P, io), o1, sf);
+    store_pop(at(dst + 2 * P, io), o2, sf);
+    store_pop(at(dst + 3 * P, io), o3, sf);
+    store_pop(at(dst + 4 * P, io), o4, sf);
+    store_pop(at(dst + 5 * P, io), o5, sf);
+    store_pop(at(dst + 6 * P, io), o6, sf);
+    store_pop(at(dst + 7 * P, io), o7, sf);
+    store_pop(at(dst + 8 * P, io), o8, sf);
   }
 
   // ---- D2Q5 collisions (Eqs. 32, 33) ----
   {
     const C c1 = C(5) * k.varpi - C(4);  // -4 + 5 varpi
-    const C ip = C(1) / phi;
+    const C ip = rphi;
     const C Tf = thf + k.T_ref;
     const C sg = k.sg;
     // fluid phase, equilibria of Eq. 37, source moments (Sr, 0, 0, c1 Sr, 0)
@@ -363,11 +404,11 @@ __global__ __launch_bounds__(kBlock) void step_kernel(
       const C r1 = o0 + h1 + o3 + o4, r2 = o0 + h2 + o3 - o4;
       const C r3 = o0 - h1 + o3 + o4, r4 = o0 - h2 + o3 - o4;
       // rest population from the conserved zeroth moment (see the flow part)
-      store_pop(dst + 9 * P + io, nf0 - ((r1 + r2) + (r3 + r4)), sg);
-      store_pop(dst + 10 * P + io, r1, sg);
-      store_pop(dst + 11 * P + io, r2, sg);
-      store_pop(dst + 12 * P + io, r3, sg);
-      store_pop(dst + 13 * P + io, r4, sg);
+      store_pop(at(dst + 9 * P, io), nf0 - ((r1 + r2) + (r3 + r4)), sg);
+      store_pop(at(dst + 10 * P, io), r1, sg);
+      store_pop(at(dst + 11 * P, io), r2, sg);
+      store_pop(at(dst + 12 * P, io), r3, sg);
+      store_pop(at(dst + 13 * P, io), r4, sg);
     }
     // solid phase, equilibria of Eq. 38
     {
@@ -384,12 +425,36 @@ __global__ __launch_bounds__(kBlock) void step_kernel(
       const C h1 = ns1 * C(0.5), h2 = ns2 * C(0.5);
       const C r1 = o0 + h1 + o3 + o4, r2 = o0 + h2 + o3 - o4;
       const C r3 = o0 - h1 + o3 + o4, r4 = o0 - h2 + o3 - o4;
-      store_pop(dst + 14 * P + io, nsol0 - ((r1 + r2) + (r3 + r4)), sg);
-      store_pop(dst + 15 * P + io, r1, sg);
-      store_pop(dst + 16 * P + io, r2, sg);
-      store_pop(dst + 17 * P + io, r3, sg);
-      store_pop(dst + 18 * P + io, r4, sg);
+      store_pop(at(dst + 14 * P, io), nsol0 - ((r1 + r2) + (r3 + r4)), sg);
+      store_pop(at(dst + 15 * P, io), r1, sg);
+      store_pop(at(dst + 16 * P, io), r2, sg);
+      store_pop(at(dst + 17 * P, io), r3, sg);
+      store_pop(at(dst + 18 * P, io), r4, sg);
     }
+  }
+}
+
+// Workgroup b runs tile (b % 8) * per_xcd + b / 8 (see TileMap); each thread
+// updates kRows nodes of one column of the tile, kRowStride rows apart.
+template <typename S, typename C, int F>
+__global__ __launch_bounds__(kBlock) void step_kernel(
+    const S* __restrict__ src, S* __restrict__ dst, const C* __restrict__ phi_field,
+    const C* __restrict__ hv_field, C* __restrict__ mac, const C* __restrict__ init_tf,
+    const C* __restrict__ init_ts, const StepConsts<C> k) {
+  const int b = blockIdx.x;
+  const int t = kXcdRemap ? (b & (kXcds - 1)) * k.tm.per_xcd + (b >> 3) : b;
+  if (t >= k.tm.ntiles) return;
+  const int tx = t % k.tm.ntx;
+  const int ty = t / k.tm.ntx;
+  const int tw = 1 << k.tm.tw_shift;
+  const int th = kBlock >> k.tm.tw_shift;
+  const int x = tx * tw + (static_cast<int>(threadIdx.x) & (tw - 1));
+  const int y0 = ty * th * kRows + (static_cast<int>(threadIdx.x) >> k.tm.tw_shift);
+  if (x >= k.nx) return;
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int y = y0 + r * th;
+    if (y < k.ny) node_update<S, C, F>(x, y, src, dst, phi_field, hv_field, mac, init_tf, init_ts, k);
   }
 }
 
