@@ -98,6 +98,46 @@ def time_form(tag: str, steps: int, warmup: int, inputs):
                 frac=achieved / HBM_PEAK_GBS, bytes_per_launch=BYTES_PER_LUP[tag] * cells)
 
 
+def time_batch(steps: int, warmup: int, autotune: bool = True):
+    """The 256-cavity batch (sides 64..512, seeded parameters), FP32, one
+    launch per step over all lattices (the faster mode; the persistent
+    launch is timed too); aggregate node updates per second."""
+    import torch
+    from paper_1608_04118_amd import binding as B
+    from paper_1608_04118_amd import inputs as I
+    ps = I.batch()
+    bt = B.Batch(ps)
+    tuned_ms = bt.autotune(reps=3) if autotune else None
+    if warmup:
+        bt.step(warmup)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(bt.stream)
+    bt.step(steps)
+    t1.record(bt.stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    info = bt.info()
+    bt.set_mode(1)
+    p0 = torch.cuda.Event(enable_timing=True)
+    p1 = torch.cuda.Event(enable_timing=True)
+    p0.record(bt.stream)
+    bt.step(steps)
+    p1.record(bt.stream)
+    torch.cuda.synchronize()
+    ms_persistent = p0.elapsed_time(p1) / steps
+    bt.macros(0)  # synchronizes and checks the barrier flag
+    bt.close()
+    nodes = info["nodes"]
+    ms_step = ms / steps
+    achieved = 152 * nodes / (ms_step * 1e-3) / 1e9
+    return dict(ms_per_step=ms_step, mlups=nodes * steps / (ms * 1e-3) / 1e6, achieved_gbs=achieved,
+                frac=achieved / HBM_PEAK_GBS, nodes=nodes, lattices=len(ps), grid=info["grid"],
+                mode="one launch per step", persistent_ms_per_step=ms_persistent,
+                autotune_ms=tuned_ms)
+
+
 def copy_bandwidth(gib: float = 1.0, reps: int = 5):
     """Plain device copy of a known size (torch's copy kernel): the
     reference kernel for the rocprofv3 byte counters, and a practical
@@ -186,6 +226,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--forms", default="f32,f64,f16s")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-cavity batch workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-check", action="store_true",
                     help="also time a plain 1 GiB device copy (reference for the byte counters)")
@@ -216,6 +257,12 @@ def main():
         print("[bench] %s: %.3f ms/step, %.0f MLUPS, %.0f GB/s" % (
             tag, res[tag]["ms_per_step"], res[tag]["mlups"], res[tag]["achieved_gbs"]),
             file=sys.stderr, flush=True)
+    batch = None
+    if not args.no_batch:
+        print("[bench] timing the 256-cavity batch (FP32)", file=sys.stderr, flush=True)
+        batch = time_batch(args.steps, args.warmup)
+        print("[bench] batch: %.3f ms/step, %.0f MLUPS, %.0f GB/s" % (
+            batch["ms_per_step"], batch["mlups"], batch["achieved_gbs"]), file=sys.stderr, flush=True)
     copy = None
     if args.copy_check:
         print("[bench] timing a plain 1 GiB device copy", file=sys.stderr, flush=True)
@@ -249,6 +296,7 @@ def main():
         "copy_reference": copy,
         "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                          for kk, vv in v.items()} for k, v in res.items()},
+        "batch256_f32": batch,
     }
     print(json.dumps(out), flush=True)
 

@@ -210,6 +210,42 @@ int lbm_ltne_get_derived(lbm_ltne_t h, lbm_ltne_derived *d);
  * NULL is accepted. */
 int lbm_ltne_destroy(lbm_ltne_t h);
 
+/*
+ * Batched lattices: n independent lattices of uneven size and parameters
+ * (one precision per batch) advanced together.  By default (mode 0) a batch
+ * step is one launch over the combined tile list of all lattices; mode 1
+ * runs all steps of a call in one persistent cooperative launch with a
+ * grid-wide barrier between steps (every barrier wait is bounded; a timeout
+ * is reported as LBM_EHIP by the next synchronizing call).  Every lattice
+ * evolves exactly as a single lattice with the same parameters would.
+ *   ps: n parameter sets; phi_fields, Hv_fields: NULL, or n pointers each
+ *   NULL or nx*ny doubles (copied).  The batch owns its device memory.
+ */
+int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params *ps, const double *const *phi_fields,
+                          const double *const *Hv_fields, void *hip_stream, lbm_ltne_batch_t *out);
+int lbm_ltne_batch_step(lbm_ltne_batch_t b, int64_t nsteps);
+int64_t lbm_ltne_batch_steps_done(lbm_ltne_batch_t b);
+/* Macros of lattice i (host arrays of nx*ny doubles, any may be NULL). */
+int lbm_ltne_batch_macros(lbm_ltne_batch_t b, int32_t i, double *rho, double *ux, double *uy,
+                          double *Tf, double *Ts);
+/* Mean Nusselt numbers of lattice i (definition of lbm_ltne_nusselt). */
+int lbm_ltne_batch_nusselt(lbm_ltne_batch_t b, int32_t i, double *Nu_f, double *Nu_s);
+/* 0: one launch per step (default), 1: persistent cooperative launch (LBM_EUNSUPPORTED if the
+ * device cannot keep a grid resident). */
+int lbm_ltne_batch_set_mode(lbm_ltne_batch_t b, int32_t persistent);
+/* Total nodes, tiles, persistent grid size (workgroups) and current mode. */
+int lbm_ltne_batch_info(lbm_ltne_batch_t b, int64_t *nodes, int32_t *tiles, int32_t *grid,
+                        int32_t *persistent);
+/* Tile width of each lattice as log2 (6, 7, 8 = 64, 128, 256 nodes wide; 0 = default). */
+int lbm_ltne_batch_set_tiles(lbm_ltne_batch_t b, const int32_t *tile_shift);
+int lbm_ltne_batch_get_tiles(lbm_ltne_batch_t b, int32_t *tile_shift);
+/* Autotuner: for each size class (lattices of equal nx) tries tile widths
+ * 64/128/256 by timing reps batch steps from a snapshot of the state (the
+ * state is restored afterwards) and keeps the fastest; ms_per_step (may be
+ * NULL) receives the best time per step. */
+int lbm_ltne_batch_autotune(lbm_ltne_batch_t b, int32_t reps, double *ms_per_step);
+int lbm_ltne_batch_destroy(lbm_ltne_batch_t b);
+
 /* Static description of a return code. */
 const char *lbm_ltne_strerror(int code);
 

@@ -91,6 +91,18 @@ def lib():
             "lbm_ltne_load": ([vp, vp, sz], C.c_int),
             "lbm_ltne_get_derived": ([vp, D], C.c_int),
             "lbm_ltne_destroy": ([vp], C.c_int),
+            "lbm_ltne_batch_create": ([i32, P, vp, vp, vp, C.POINTER(vp)], C.c_int),
+            "lbm_ltne_batch_step": ([vp, i64], C.c_int),
+            "lbm_ltne_batch_steps_done": ([vp], i64),
+            "lbm_ltne_batch_macros": ([vp, i32, vp, vp, vp, vp, vp], C.c_int),
+            "lbm_ltne_batch_nusselt": ([vp, i32, dp, dp], C.c_int),
+            "lbm_ltne_batch_set_mode": ([vp, i32], C.c_int),
+            "lbm_ltne_batch_info": ([vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32),
+                                     C.POINTER(i32)], C.c_int),
+            "lbm_ltne_batch_set_tiles": ([vp, vp], C.c_int),
+            "lbm_ltne_batch_get_tiles": ([vp, vp], C.c_int),
+            "lbm_ltne_batch_autotune": ([vp, i32, dp], C.c_int),
+            "lbm_ltne_batch_destroy": ([vp], C.c_int),
             "lbm_ltne_strerror": ([C.c_int], C.c_char_p),
             "lbm_ltne_last_error": ([], C.c_char_p),
             "lbm_ltne_abi_version": ([], C.c_int),
@@ -312,6 +324,156 @@ class Lattice:
             lbm_ltne_destroy(self.h)
             self.h = None
         self._pool = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --- batched lattices -----------------------------------------------------------
+
+def lbm_ltne_batch_create(params_list, phi_fields=None, Hv_fields=None, hip_stream=None):
+    ps = [_as_params(p) for p in params_list]
+    n = len(ps)
+    arr = (lbm_ltne_params * n)(*ps)
+    keep = []
+
+    def ptrs(fields):
+        if fields is None:
+            return None
+        out = (C.c_void_p * n)()
+        for i, f in enumerate(fields):
+            if f is not None:
+                a = _field(f, ps[i].nx * ps[i].ny)
+                keep.append(a)
+                out[i] = a.ctypes.data
+        return out
+
+    pp, hp = ptrs(phi_fields), ptrs(Hv_fields)
+    h = C.c_void_p()
+    rc = lib().lbm_ltne_batch_create(n, arr, C.cast(pp, C.c_void_p) if pp is not None else None,
+                                     C.cast(hp, C.c_void_p) if hp is not None else None,
+                                     C.c_void_p(hip_stream) if hip_stream else None, C.byref(h))
+    _check(rc, "lbm_ltne_batch_create")
+    return h
+
+
+def lbm_ltne_batch_step(b, nsteps):
+    _check(lib().lbm_ltne_batch_step(b, int(nsteps)), "lbm_ltne_batch_step")
+
+
+def lbm_ltne_batch_macros(b, i, nx, ny):
+    out = {k: np.empty((ny, nx)) for k in ("rho", "ux", "uy", "Tf", "Ts")}
+    _check(lib().lbm_ltne_batch_macros(b, int(i), *[_ptr(out[k]) for k in ("rho", "ux", "uy", "Tf", "Ts")]),
+           "lbm_ltne_batch_macros")
+    return out
+
+
+def lbm_ltne_batch_nusselt(b, i):
+    a, c = C.c_double(), C.c_double()
+    _check(lib().lbm_ltne_batch_nusselt(b, int(i), C.byref(a), C.byref(c)), "lbm_ltne_batch_nusselt")
+    return a.value, c.value
+
+
+def lbm_ltne_batch_set_mode(b, persistent):
+    _check(lib().lbm_ltne_batch_set_mode(b, int(persistent)), "lbm_ltne_batch_set_mode")
+
+
+def lbm_ltne_batch_info(b):
+    n, t, g, m = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().lbm_ltne_batch_info(b, C.byref(n), C.byref(t), C.byref(g), C.byref(m)),
+           "lbm_ltne_batch_info")
+    return dict(nodes=n.value, tiles=t.value, grid=g.value, persistent=m.value)
+
+
+def lbm_ltne_batch_set_tiles(b, shifts):
+    a = np.ascontiguousarray(np.asarray(shifts, dtype=np.int32))
+    _check(lib().lbm_ltne_batch_set_tiles(b, _ptr(a)), "lbm_ltne_batch_set_tiles")
+
+
+def lbm_ltne_batch_get_tiles(b, n):
+    a = np.zeros(n, dtype=np.int32)
+    _check(lib().lbm_ltne_batch_get_tiles(b, _ptr(a)), "lbm_ltne_batch_get_tiles")
+    return a
+
+
+def lbm_ltne_batch_autotune(b, reps=4):
+    ms = C.c_double()
+    _check(lib().lbm_ltne_batch_autotune(b, int(reps), C.byref(ms)), "lbm_ltne_batch_autotune")
+    return ms.value
+
+
+def lbm_ltne_batch_destroy(b):
+    _check(lib().lbm_ltne_batch_destroy(b), "lbm_ltne_batch_destroy")
+
+
+class Batch:
+    """Many independent lattices advanced together on the current torch
+    stream (persistent launch by default)."""
+
+    def __init__(self, params_list, phi_fields=None, Hv_fields=None, use_torch=True):
+        self.ps = [_as_params(p) for p in params_list]
+        stream = None
+        if use_torch:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+            self.stream = torch.cuda.current_stream()
+        self.h = lbm_ltne_batch_create(self.ps, phi_fields, Hv_fields, stream)
+
+    def __len__(self):
+        return len(self.ps)
+
+    def step(self, n=1):
+        lbm_ltne_batch_step(self.h, n)
+        return self
+
+    def macros(self, i):
+        return lbm_ltne_batch_macros(self.h, i, self.ps[i].nx, self.ps[i].ny)
+
+    def nusselt(self, i):
+        return lbm_ltne_batch_nusselt(self.h, i)
+
+    def set_mode(self, persistent):
+        lbm_ltne_batch_set_mode(self.h, persistent)
+
+    def info(self):
+        return lbm_ltne_batch_info(self.h)
+
+    def tiles(self):
+        return lbm_ltne_batch_get_tiles(self.h, len(self.ps))
+
+    def set_tiles(self, shifts):
+        lbm_ltne_batch_set_tiles(self.h, shifts)
+
+    def autotune(self, reps=4, cache=None):
+        """Tile widths per size class.  With ``cache`` (a JSON path), a
+        choice stored for this device, precision and lattice width is reused
+        and new choices are added; the key is "gfx950/<precision>/<nx>"."""
+        import json
+        key = lambda p: "gfx950/%d/%d" % (p.precision, p.nx)
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if table and all(key(p) in table for p in self.ps):
+            self.set_tiles([table[key(p)] for p in self.ps])
+            return None
+        ms = lbm_ltne_batch_autotune(self.h, reps)
+        if cache:
+            for p, sh in zip(self.ps, self.tiles()):
+                table[key(p)] = int(sh)
+            d = os.path.dirname(os.path.abspath(cache))
+            os.makedirs(d, exist_ok=True)
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+        return ms
+
+    def close(self):
+        if getattr(self, "h", None):
+            lbm_ltne_batch_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

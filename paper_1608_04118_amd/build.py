@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm_ltne.so")
-SOURCES = ["lbm_ltne.hip", "params.hip"]
+SOURCES = ["lbm_ltne.hip", "params.hip", "batch.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

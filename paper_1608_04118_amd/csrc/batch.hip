@@ -1,0 +1,643 @@
+// Batched execution: many independent lattices of uneven size and
+// parameters advanced together, either by one launch per step over the
+// combined tile list (the default), or by one persistent cooperative launch
+// that loops over the time steps with a grid-wide barrier between steps.
+// On MI355X the barrier's device-scope release and acquire (L2 write-back
+// and invalidation on every XCD, once per resident workgroup) cost more than
+// a kernel launch per step, so the per-step form is the default.  Every lattice keeps
+// its own populations, parameter block and macro buffer; the per-node update
+// is the same node_update as the single-lattice kernel.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "host_common.hpp"
+#include "lbm_ltne.h"
+#include "params.hpp"
+#include "reduce_kernels.hpp"
+#include "step_kernel.hpp"
+
+namespace ltne {
+
+template <typename C>
+struct CavityDesc {
+  void* pop[2];     // population buffers (storage type), ping-pong
+  const C* phi;     // per-node porosity or nullptr
+  const C* hv;      // per-node interphase coefficient or nullptr
+  C* mac;           // macros of the last step (5 planes of nx*ny)
+  int tile_begin;   // first entry of this lattice in the combined tile list
+  int pad_;
+};
+
+// Grid barrier state, zeroed by the host before each persistent launch.
+struct BatchCtl {
+  unsigned count;       // workgroups arrived at the current barrier
+  unsigned generation;  // barriers completed
+  int error;            // 1: a wait exceeded its spin limit (all workgroups then leave)
+  int pad_;
+};
+
+template <typename S, typename C, int F>
+__device__ __forceinline__ void batch_tile(int t, const CavityDesc<C>* __restrict__ cav,
+                                           const StepConsts<C>* __restrict__ ks,
+                                           const int* __restrict__ tile_cav, int parity, bool macros) {
+  const int c = tile_cav[t];
+  const StepConsts<C>& k = ks[c];
+  const CavityDesc<C>& d = cav[c];
+  const int lt = t - d.tile_begin;
+  const int tx = lt % k.tm.ntx;
+  const int ty = lt / k.tm.ntx;
+  const int tw = 1 << k.tm.tw_shift;
+  const int th = kBlock >> k.tm.tw_shift;
+  const int x = tx * tw + (static_cast<int>(threadIdx.x) & (tw - 1));
+  const int y0 = ty * th * kRows + (static_cast<int>(threadIdx.x) >> k.tm.tw_shift);
+  if (x >= k.nx) return;
+  const S* src = static_cast<const S*>(d.pop[parity]);
+  S* dst = static_cast<S*>(d.pop[parity ^ 1]);
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int y = y0 + r * th;
+    if (y >= k.ny) continue;
+    if (macros)
+      node_update<S, C, F | kMacros>(x, y, src, dst, d.phi, d.hv, d.mac, nullptr, nullptr, k);
+    else
+      node_update<S, C, F>(x, y, src, dst, d.phi, d.hv, nullptr, nullptr, nullptr, k);
+  }
+}
+
+// Grid-wide barrier for a co-resident (cooperative) grid.  Every wave waits
+// for its own stores, thread 0 of each workgroup releases them device-wide,
+// arrives, and waits for the generation to move on -- at most spin_limit
+// polls, after which it raises the error flag and reports failure so the
+// whole grid leaves the step loop.
+__device__ __forceinline__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks, unsigned& gen,
+                                             unsigned spin_limit) {
+  __shared__ int ok;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ok = 1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned target = gen + 1;
+    const unsigned arrived =
+        __hip_atomic_fetch_add(&ctl->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+    if (arrived == nblocks) {
+      __hip_atomic_store(&ctl->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->generation, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(&ctl->generation, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++spins > spin_limit ||
+            __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(8);
+      }
+    }
+    gen = target;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// nsteps time steps of every lattice.  The tile list is split into 8
+// contiguous ranges, one per XCD (workgroup b runs on XCD b % 8); the grid
+// has a multiple of 8 workgroups.  With persistent = 0 the kernel does one
+// step and needs no barrier.
+template <typename S, typename C, int F>
+__global__ __launch_bounds__(kBlock) void batch_kernel(
+    const CavityDesc<C>* __restrict__ cav, const StepConsts<C>* __restrict__ ks,
+    const int* __restrict__ tile_cav, int ntiles, int nsteps, int parity0, int macros_last,
+    BatchCtl* ctl, unsigned spin_limit) {
+  const int xcd = blockIdx.x & (kXcds - 1);
+  const int slot = blockIdx.x >> 3;
+  const int slots = gridDim.x >> 3;
+  const int per = (ntiles + kXcds - 1) / kXcds;
+  const int t0 = xcd * per;
+  const int t1 = min(ntiles, t0 + per);
+  unsigned gen = 0;
+  for (int s = 0; s < nsteps; ++s) {
+    const int parity = (parity0 + s) & 1;
+    const bool macros = macros_last && (s == nsteps - 1);
+    for (int t = t0 + slot; t < t1; t += slots) batch_tile<S, C, F>(t, cav, ks, tile_cav, parity, macros);
+    if (s + 1 < nsteps && !grid_barrier(ctl, gridDim.x, gen, spin_limit)) return;
+  }
+}
+
+}  // namespace ltne
+
+using namespace ltne;
+
+struct lbm_ltne_batch {
+  int n = 0;
+  int precision = LBM_FP32;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::vector<lbm_ltne_params> p;
+  std::vector<lbm_ltne_derived> d;
+  std::vector<int> shift;  // tile width shift per lattice
+  char* base = nullptr;    // all device memory of the batch
+  size_t bytes = 0;
+  std::vector<size_t> off_pop0, off_pop1, off_phi, off_hv, off_mac;
+  size_t off_cav = 0, off_consts = 0, off_tiles = 0, off_ctl = 0, off_result = 0;
+  int ntiles = 0;
+  int max_tiles = 0;
+  int fields = 0;     // kPhiField / kHvField if any lattice has that field
+  int parity = 0;     // buffer holding the current state
+  int64_t steps = 0;
+  int persistent = 0; // 1: cooperative persistent launch, 0: one launch per step (default, faster)
+  int grid = 0;       // workgroups of the persistent launch
+  size_t consts_bytes = 0, desc_bytes = 0;
+  long long nodes = 0;
+
+  long long n_of(int i) const { return static_cast<long long>(p[i].nx) * p[i].ny; }
+};
+
+namespace {
+
+void batch_release(lbm_ltne_batch* b) {
+  if (!b) return;
+  if (b->base) (void)hipFree(b->base);
+  delete b;
+}
+
+template <typename C>
+int upload_tables_t(lbm_ltne_batch* b) {
+  std::vector<StepConsts<C>> ks(b->n);
+  std::vector<CavityDesc<C>> cav(b->n);
+  std::vector<int> tile_cav;
+  tile_cav.reserve(b->max_tiles);
+  for (int i = 0; i < b->n; ++i) {
+    fill_step_consts(b->p[i], b->d[i], &ks[i]);
+    ks[i].tm = make_tiles(b->p[i].nx, b->p[i].ny, b->precision, b->shift[i]);
+    cav[i].pop[0] = b->base + b->off_pop0[i];
+    cav[i].pop[1] = b->base + b->off_pop1[i];
+    cav[i].phi = b->off_phi[i] ? reinterpret_cast<const C*>(b->base + b->off_phi[i]) : nullptr;
+    cav[i].hv = b->off_hv[i] ? reinterpret_cast<const C*>(b->base + b->off_hv[i]) : nullptr;
+    cav[i].mac = reinterpret_cast<C*>(b->base + b->off_mac[i]);
+    cav[i].tile_begin = static_cast<int>(tile_cav.size());
+    for (int t = 0; t < ks[i].tm.ntiles; ++t) tile_cav.push_back(i);
+  }
+  b->ntiles = static_cast<int>(tile_cav.size());
+  HIP_TRY(hipMemcpyAsync(b->base + b->off_consts, ks.data(), ks.size() * sizeof(ks[0]),
+                         hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->base + b->off_cav, cav.data(), cav.size() * sizeof(cav[0]),
+                         hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->base + b->off_tiles, tile_cav.data(), tile_cav.size() * sizeof(int),
+                         hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+int upload_tables(lbm_ltne_batch* b) {
+  return b->precision == LBM_FP64 ? upload_tables_t<double>(b) : upload_tables_t<float>(b);
+}
+
+template <typename S, typename C, int F>
+const void* batch_fn() {
+  return reinterpret_cast<const void*>(&batch_kernel<S, C, F>);
+}
+
+template <typename S, typename C>
+const void* pick_fn(int fields) {
+  switch (fields) {
+    case kPhiField: return batch_fn<S, C, kPhiField>();
+    case kHvField: return batch_fn<S, C, kHvField>();
+    case kPhiField | kHvField: return batch_fn<S, C, kPhiField | kHvField>();
+    default: return batch_fn<S, C, 0>();
+  }
+}
+
+const void* batch_function(const lbm_ltne_batch* b) {
+  if (b->precision == LBM_FP64) return pick_fn<double, double>(b->fields);
+  if (b->precision == LBM_FP32) return pick_fn<float, float>(b->fields);
+  return pick_fn<_Float16, float>(b->fields);
+}
+
+// Workgroups that can be resident at once (multiple of 8), for the
+// cooperative launch.
+int resident_grid(const lbm_ltne_batch* b, int* out) {
+  int per_cu = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_function(b), kBlock, 0));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, b->device));
+  int g = per_cu * prop.multiProcessorCount;
+  g -= g % kXcds;
+  *out = g;
+  return LBM_OK;
+}
+
+constexpr unsigned kSpinLimit = 1u << 24;
+
+int launch_batch(lbm_ltne_batch* b, int nsteps, int macros_last) {
+  const void* fn = batch_function(b);
+  const void* cav = b->base + b->off_cav;
+  const void* ks = b->base + b->off_consts;
+  const void* tiles = b->base + b->off_tiles;
+  BatchCtl* ctl = reinterpret_cast<BatchCtl*>(b->base + b->off_ctl);
+  int ntiles = b->ntiles;
+  unsigned spin = kSpinLimit;
+  if (b->persistent) {
+    HIP_TRY(hipMemsetAsync(ctl, 0, sizeof(BatchCtl), b->stream));
+    int parity = b->parity;
+    void* args[] = {&cav, &ks, &tiles, &ntiles, &nsteps, &parity, &macros_last, &ctl, &spin};
+    HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(b->grid), dim3(kBlock), args, 0, b->stream));
+  } else {
+    const int per = (ntiles + kXcds - 1) / kXcds;
+    const int grid = kXcds * per;  // one tile per workgroup per step
+    for (int s = 0; s < nsteps; ++s) {
+      int one = 1;
+      int parity = (b->parity + s) & 1;
+      int mac = (macros_last && s == nsteps - 1) ? 1 : 0;
+      void* args[] = {&cav, &ks, &tiles, &ntiles, &one, &parity, &mac, &ctl, &spin};
+      HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, b->stream));
+    }
+  }
+  b->parity = (b->parity + nsteps) & 1;
+  return LBM_OK;
+}
+
+int check_ctl(lbm_ltne_batch* b) {
+  BatchCtl c;
+  HIP_TRY(hipMemcpyAsync(&c, b->base + b->off_ctl, sizeof(c), hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (c.error) return set_error(LBM_EHIP, "a grid barrier of the persistent batch launch timed out");
+  return LBM_OK;
+}
+
+template <typename S, typename C>
+hipError_t init_one(const lbm_ltne_batch* b, int i) {
+  StepConsts<C> k;
+  fill_step_consts(b->p[i], b->d[i], &k);
+  k.tm = make_tiles(b->p[i].nx, b->p[i].ny, b->precision, b->shift[i]);
+  const C* phi = b->off_phi[i] ? reinterpret_cast<const C*>(b->base + b->off_phi[i]) : nullptr;
+  const C* hv = b->off_hv[i] ? reinterpret_cast<const C*>(b->base + b->off_hv[i]) : nullptr;
+  S* dst = reinterpret_cast<S*>(b->base + b->off_pop0[i]);
+  C* mac = reinterpret_cast<C*>(b->base + b->off_mac[i]);
+  const dim3 grid(grid_blocks(k.tm)), block(kBlock);
+  const int fl = (phi ? kPhiField : 0) | (hv ? kHvField : 0);
+  switch (fl) {
+    case 0:
+      hipLaunchKernelGGL((step_kernel<S, C, kMacros | kInit>), grid, block, 0, b->stream, nullptr,
+                         dst, phi, hv, mac, nullptr, nullptr, k);
+      break;
+    case kPhiField:
+      hipLaunchKernelGGL((step_kernel<S, C, kPhiField | kMacros | kInit>), grid, block, 0, b->stream,
+                         nullptr, dst, phi, hv, mac, nullptr, nullptr, k);
+      break;
+    case kHvField:
+      hipLaunchKernelGGL((step_kernel<S, C, kHvField | kMacros | kInit>), grid, block, 0, b->stream,
+                         nullptr, dst, phi, hv, mac, nullptr, nullptr, k);
+      break;
+    default:
+      hipLaunchKernelGGL((step_kernel<S, C, kPhiField | kHvField | kMacros | kInit>), grid, block, 0,
+                         b->stream, nullptr, dst, phi, hv, mac, nullptr, nullptr, k);
+  }
+  return hipGetLastError();
+}
+
+hipError_t init_lattice(const lbm_ltne_batch* b, int i) {
+  if (b->precision == LBM_FP64) return init_one<double, double>(b, i);
+  if (b->precision == LBM_FP32) return init_one<float, float>(b, i);
+  return init_one<_Float16, float>(b, i);
+}
+
+int upload_batch_field(const lbm_ltne_batch* b, const double* src, size_t off, long long n) {
+  if (b->precision == LBM_FP64) {
+    HIP_TRY(hipMemcpyAsync(b->base + off, src, n * sizeof(double), hipMemcpyHostToDevice, b->stream));
+  } else {
+    std::vector<float> tmp(n);
+    for (long long j = 0; j < n; ++j) tmp[j] = static_cast<float>(src[j]);
+    HIP_TRY(hipMemcpyAsync(b->base + off, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params* ps, const double* const* phi_fields,
+                          const double* const* Hv_fields, void* hip_stream, lbm_ltne_batch_t* out) {
+  clear_error();
+  if (!out) return set_error(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n <= 0 || !ps) return set_error(LBM_EINVAL, "need n > 0 parameter sets");
+  const int precision = ps[0].precision;
+  std::vector<lbm_ltne_derived> ds(n);
+  for (int i = 0; i < n; ++i) {
+    if (ps[i].precision != precision)
+      return set_error(LBM_EINVAL, "lattice %d: all lattices of a batch share one precision", i);
+    double lo, hi;
+    temperature_range(&ps[i], &lo, &hi);
+    const int rc = derive(&ps[i], lo, hi, &ds[i]);
+    if (rc != LBM_OK) {
+      std::string msg = last_error();
+      return set_error(rc, "lattice %d: %s", i, msg.c_str());
+    }
+    const long long nn = static_cast<long long>(ps[i].nx) * ps[i].ny;
+    if (phi_fields && phi_fields[i])
+      for (long long j = 0; j < nn; ++j)
+        if (!(phi_fields[i][j] > 0.0 && phi_fields[i][j] < 1.0))
+          return set_error(LBM_EINVAL, "lattice %d: phi_field[%lld] not in (0, 1)", i, j);
+    if (Hv_fields && Hv_fields[i])
+      for (long long j = 0; j < nn; ++j)
+        if (!(Hv_fields[i][j] >= 0.0) || !std::isfinite(Hv_fields[i][j]))
+          return set_error(LBM_EINVAL, "lattice %d: Hv_field[%lld] must be finite and >= 0", i, j);
+  }
+  int dev = 0;
+  int rc = check_device(&dev);
+  if (rc != LBM_OK) return rc;
+  lbm_ltne_batch* b = new (std::nothrow) lbm_ltne_batch();
+  if (!b) return set_error(LBM_ENOMEM, "host allocation failed");
+  b->n = n;
+  b->precision = precision;
+  b->device = dev;
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->p.assign(ps, ps + n);
+  b->d = ds;
+  b->shift.assign(n, 0);
+  for (int i = 0; i < n; ++i) {
+    if (phi_fields && phi_fields[i]) b->fields |= kPhiField;
+    if (Hv_fields && Hv_fields[i]) b->fields |= kHvField;
+  }
+  // Layout: per lattice two population buffers, fields, macros; then the
+  // tables.  A lattice without a field gets the uniform value materialised
+  // when another lattice of the batch has one (one kernel variant per batch).
+  size_t o = 0;
+  b->off_pop0.resize(n);
+  b->off_pop1.resize(n);
+  b->off_phi.assign(n, 0);
+  b->off_hv.assign(n, 0);
+  b->off_mac.resize(n);
+  const size_t sb = storage_bytes(precision), cb = compute_bytes(precision);
+  for (int i = 0; i < n; ++i) {
+    const long long nn = b->n_of(i);
+    const size_t popb = align_up(kPlanes * plane_elems(ps[i].nx, ps[i].ny, precision) * sb, kAlign);
+    b->off_pop0[i] = o; o += popb;
+    b->off_pop1[i] = o; o += popb;
+    if (b->fields & kPhiField) { b->off_phi[i] = o; o += align_up(nn * cb, kAlign); }
+    if (b->fields & kHvField) { b->off_hv[i] = o; o += align_up(nn * cb, kAlign); }
+    b->off_mac[i] = o; o += align_up(5 * nn * cb, kAlign);
+    b->nodes += nn;
+    int most = 0;  // the tile table must hold the tiles of any width choice
+    for (int sh = 6; sh <= 8; ++sh) most = std::max(most, make_tiles(ps[i].nx, ps[i].ny, precision, sh).ntiles);
+    b->max_tiles += most;
+  }
+  b->consts_bytes = (precision == LBM_FP64 ? sizeof(StepConsts<double>) : sizeof(StepConsts<float>));
+  b->desc_bytes = (precision == LBM_FP64 ? sizeof(CavityDesc<double>) : sizeof(CavityDesc<float>));
+  b->off_consts = o; o += align_up(n * b->consts_bytes, kAlign);
+  b->off_cav = o; o += align_up(n * b->desc_bytes, kAlign);
+  b->off_tiles = o; o += align_up(static_cast<size_t>(b->max_tiles) * sizeof(int), kAlign);
+  b->off_ctl = o; o += kAlign;
+  b->off_result = o; o += kAlign;
+  b->bytes = o;
+  if (hipMalloc(&b->base, b->bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    const size_t want = b->bytes;
+    b->base = nullptr;
+    batch_release(b);
+    return set_error(LBM_ENOMEM, "hipMalloc of %zu bytes failed", want);
+  }
+  rc = LBM_OK;
+  for (int i = 0; i < n && rc == LBM_OK; ++i) {
+    const long long nn = b->n_of(i);
+    std::vector<double> fill;
+    if (b->fields & kPhiField) {
+      const double* src = (phi_fields && phi_fields[i]) ? phi_fields[i] : nullptr;
+      if (!src) { fill.assign(nn, ps[i].phi); src = fill.data(); }
+      rc = upload_batch_field(b, src, b->off_phi[i], nn);
+    }
+    if (rc == LBM_OK && (b->fields & kHvField)) {
+      const double* src = (Hv_fields && Hv_fields[i]) ? Hv_fields[i] : nullptr;
+      if (!src) { fill.assign(nn, ps[i].Hv); src = fill.data(); }
+      rc = upload_batch_field(b, src, b->off_hv[i], nn);
+    }
+    if (rc == LBM_OK) {
+      hipError_t e = init_lattice(b, i);
+      if (e != hipSuccess) rc = set_error(LBM_EHIP, "initialisation of lattice %d: %s", i, hipGetErrorString(e));
+    }
+  }
+  if (rc == LBM_OK) rc = upload_tables(b);
+  if (rc == LBM_OK) rc = resident_grid(b, &b->grid);
+
+  if (rc == LBM_OK) {
+    hipError_t e = hipMemsetAsync(b->base + b->off_ctl, 0, sizeof(BatchCtl), b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) rc = set_error(LBM_EHIP, "batch setup: %s", hipGetErrorString(e));
+  }
+  if (rc != LBM_OK) {
+    batch_release(b);
+    return rc;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+int lbm_ltne_batch_step(lbm_ltne_batch_t b, int64_t nsteps) {
+  if (!b) return set_error(LBM_EINVAL, "batch is NULL");
+  if (nsteps < 0) return set_error(LBM_EINVAL, "nsteps < 0");
+  if (nsteps == 0) return LBM_OK;
+  // one persistent launch covers up to 2^20 steps; longer runs are split
+  int64_t left = nsteps;
+  while (left > 0) {
+    const int chunk = static_cast<int>(std::min<int64_t>(left, 1 << 20));
+    const int rc = launch_batch(b, chunk, left == chunk ? 1 : 0);
+    if (rc != LBM_OK) return rc;
+    left -= chunk;
+  }
+  b->steps += nsteps;
+  return LBM_OK;
+}
+
+int lbm_ltne_batch_set_mode(lbm_ltne_batch_t b, int32_t persistent) {
+  if (!b) return set_error(LBM_EINVAL, "batch is NULL");
+  if (persistent && b->grid < kXcds)
+    return set_error(LBM_EUNSUPPORTED, "no resident grid for a persistent launch");
+  b->persistent = persistent ? 1 : 0;
+  return LBM_OK;
+}
+
+int lbm_ltne_batch_info(lbm_ltne_batch_t b, int64_t* nodes, int32_t* tiles, int32_t* grid,
+                        int32_t* persistent) {
+  if (!b) return set_error(LBM_EINVAL, "batch is NULL");
+  if (nodes) *nodes = b->nodes;
+  if (tiles) *tiles = b->ntiles;
+  if (grid) *grid = b->grid;
+  if (persistent) *persistent = b->persistent;
+  return LBM_OK;
+}
+
+int lbm_ltne_batch_set_tiles(lbm_ltne_batch_t b, const int32_t* tile_shift) {
+  if (!b || !tile_shift) return set_error(LBM_EINVAL, "batch or shifts NULL");
+  for (int i = 0; i < b->n; ++i)
+    if (tile_shift[i] != 0 && (tile_shift[i] < 6 || tile_shift[i] > 8))
+      return set_error(LBM_EINVAL, "tile shift %d of lattice %d not in {0, 6, 7, 8}", tile_shift[i], i);
+  for (int i = 0; i < b->n; ++i) b->shift[i] = tile_shift[i];
+  return upload_tables(b);
+}
+
+int lbm_ltne_batch_get_tiles(lbm_ltne_batch_t b, int32_t* tile_shift) {
+  if (!b || !tile_shift) return set_error(LBM_EINVAL, "batch or shifts NULL");
+  for (int i = 0; i < b->n; ++i)
+    tile_shift[i] = make_tiles(b->p[i].nx, b->p[i].ny, b->precision, b->shift[i]).tw_shift;
+  return LBM_OK;
+}
+
+int lbm_ltne_batch_autotune(lbm_ltne_batch_t b, int32_t reps, double* ms_per_step) {
+  if (!b) return set_error(LBM_EINVAL, "batch is NULL");
+  if (reps <= 0) reps = 4;
+  // Snapshot the state: trial steps must not advance the simulation.
+  size_t pop_total = 0;
+  for (int i = 0; i < b->n; ++i) pop_total += b->off_pop1[i] - b->off_pop0[i];
+  char* snap = nullptr;
+  if (hipMalloc(&snap, pop_total) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(LBM_ENOMEM, "autotune snapshot of %zu bytes failed", pop_total);
+  }
+  auto copy_state = [&](bool save) -> int {
+    size_t o = 0;
+    for (int i = 0; i < b->n; ++i) {
+      const size_t sz = b->off_pop1[i] - b->off_pop0[i];
+      char* cur = b->base + (b->parity ? b->off_pop1[i] : b->off_pop0[i]);
+      HIP_TRY(hipMemcpyAsync(save ? snap + o : cur, save ? cur : snap + o, sz, hipMemcpyDeviceToDevice,
+                             b->stream));
+      o += sz;
+    }
+    return LBM_OK;
+  };
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipFree(snap);
+    return set_error(LBM_EHIP, "event creation failed");
+  }
+  const int parity0 = b->parity;
+  auto trial = [&](float* ms) -> int {
+    int rc = copy_state(false);
+    if (rc != LBM_OK) return rc;
+    b->parity = parity0;
+    rc = launch_batch(b, 1, 0);  // warm-up
+    if (rc != LBM_OK) return rc;
+    HIP_TRY(hipEventRecord(e0, b->stream));
+    rc = launch_batch(b, reps, 0);
+    if (rc != LBM_OK) return rc;
+    HIP_TRY(hipEventRecord(e1, b->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+    rc = check_ctl(b);
+    *ms /= static_cast<float>(reps);
+    b->parity = parity0;
+    return rc;
+  };
+  int rc = copy_state(true);
+  if (rc == LBM_OK) rc = (hipStreamSynchronize(b->stream) == hipSuccess) ? LBM_OK : LBM_EHIP;
+  // Coordinate descent over the size classes (lattices of equal width share
+  // a choice), starting from the defaults.
+  std::map<int, std::vector<int>> classes;
+  for (int i = 0; i < b->n; ++i) classes[b->p[i].nx].push_back(i);
+  float best = 0.0f;
+  if (rc == LBM_OK) rc = upload_tables(b);
+  if (rc == LBM_OK) rc = trial(&best);
+  for (auto& kv : classes) {
+    if (rc != LBM_OK) break;
+    const int nx = kv.first;
+    const int keep = b->shift[kv.second[0]];
+    int best_shift = keep;
+    for (int sh = 6; sh <= 8; ++sh) {
+      if ((1 << sh) > std::max(64, nx)) break;
+      for (int i : kv.second) b->shift[i] = sh;
+      rc = upload_tables(b);
+      float ms = 0.0f;
+      if (rc == LBM_OK) rc = trial(&ms);
+      if (rc != LBM_OK) break;
+      if (ms < best) {
+        best = ms;
+        best_shift = sh;
+      }
+    }
+    for (int i : kv.second) b->shift[i] = best_shift;
+  }
+  if (rc == LBM_OK) rc = upload_tables(b);
+  const int rc2 = copy_state(false);
+  if (rc == LBM_OK) rc = rc2;
+  if (hipStreamSynchronize(b->stream) != hipSuccess && rc == LBM_OK) rc = set_error(LBM_EHIP, "autotune sync");
+  b->parity = parity0;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(snap);
+  if (ms_per_step) *ms_per_step = best;
+  return rc;
+}
+
+int lbm_ltne_batch_macros(lbm_ltne_batch_t b, int32_t i, double* rho, double* ux, double* uy,
+                          double* Tf, double* Ts) {
+  if (!b) return set_error(LBM_EINVAL, "batch is NULL");
+  if (i < 0 || i >= b->n) return set_error(LBM_EINVAL, "lattice index %d out of range", i);
+  int rc = check_ctl(b);
+  if (rc != LBM_OK) return rc;
+  const long long n = b->n_of(i);
+  const size_t cb = compute_bytes(b->precision);
+  double* outs[5] = {rho, ux, uy, Tf, Ts};
+  std::vector<float> tmp;
+  for (int f = 0; f < 5; ++f) {
+    if (!outs[f]) continue;
+    const char* src = b->base + b->off_mac[i] + static_cast<size_t>(f) * n * cb;
+    if (cb == 8) {
+      HIP_TRY(hipMemcpyAsync(outs[f], src, n * 8, hipMemcpyDeviceToHost, b->stream));
+      HIP_TRY(hipStreamSynchronize(b->stream));
+    } else {
+      tmp.resize(n);
+      HIP_TRY(hipMemcpyAsync(tmp.data(), src, n * 4, hipMemcpyDeviceToHost, b->stream));
+      HIP_TRY(hipStreamSynchronize(b->stream));
+      for (long long j = 0; j < n; ++j) outs[f][j] = tmp[j];
+    }
+  }
+  return LBM_OK;
+}
+
+int lbm_ltne_batch_nusselt(lbm_ltne_batch_t b, int32_t i, double* Nu_f, double* Nu_s) {
+  if (!b) return set_error(LBM_EINVAL, "batch is NULL");
+  if (i < 0 || i >= b->n) return set_error(LBM_EINVAL, "lattice index %d out of range", i);
+  int rc = check_ctl(b);
+  if (rc != LBM_OK) return rc;
+  const lbm_ltne_params& p = b->p[i];
+  const int w = hot_wall(&p);
+  if (w < 0) return set_error(LBM_EINVAL, "lattice %d has no wall for the Nusselt number", i);
+  const int periodic_t = (w < 2) ? p.periodic_y : p.periodic_x;
+  const double scale = b->d[i].L / b->d[i].dT;
+  double* res = reinterpret_cast<double*>(b->base + b->off_result);
+  const long long n = b->n_of(i);
+  if (b->precision == LBM_FP64)
+    hipLaunchKernelGGL((nusselt_kernel<double>), dim3(1), dim3(kBlock), 0, b->stream,
+                       reinterpret_cast<const double*>(b->base + b->off_mac[i]), p.nx, p.ny, n, w,
+                       periodic_t, scale, res);
+  else
+    hipLaunchKernelGGL((nusselt_kernel<float>), dim3(1), dim3(kBlock), 0, b->stream,
+                       reinterpret_cast<const float*>(b->base + b->off_mac[i]), p.nx, p.ny, n, w,
+                       periodic_t, scale, res);
+  HIP_TRY(hipGetLastError());
+  double r[2];
+  HIP_TRY(hipMemcpyAsync(r, res, sizeof(r), hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (Nu_f) *Nu_f = r[0];
+  if (Nu_s) *Nu_s = r[1];
+  return LBM_OK;
+}
+
+int64_t lbm_ltne_batch_steps_done(lbm_ltne_batch_t b) { return b ? b->steps : -1; }
+
+int lbm_ltne_batch_destroy(lbm_ltne_batch_t b) {
+  if (!b) return LBM_OK;
+  (void)hipStreamSynchronize(b->stream);
+  batch_release(b);
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -9,80 +9,12 @@
 
 #include "common.hpp"
 #include "lbm_ltne.h"
+#include "host_common.hpp"
 #include "params.hpp"
 #include "reduce_kernels.hpp"
 #include "step_kernel.hpp"
 
 using namespace ltne;
-
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return set_error(LBM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
-  } while (0)
-
-namespace {
-
-constexpr size_t kAlign = 256;
-constexpr int kSumBlocks = 1024;
-constexpr uint32_t kStateMagic = 0x454e544cu;  // "LTNE"
-
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-size_t storage_bytes(int precision) {
-  return precision == LBM_FP64 ? 8 : (precision == LBM_FP32 ? 4 : 2);
-}
-size_t compute_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
-
-// Elements between population planes: the plane rounded up to 1024 elements
-// plus kPlanePad, so that the 19 planes do not start on the same
-// power-of-two boundary.
-long long plane_elems(int nx, int ny) {
-  const long long n = static_cast<long long>(nx) * ny;
-  return static_cast<long long>(align_up(static_cast<size_t>(n), 1024)) + kPlanePad;
-}
-
-struct Layout {
-  size_t pop_bytes, field_bytes, mac_bytes;
-  size_t off_pop[2], off_phi, off_hv, off_mac[2], off_partial, off_result;
-  size_t total;
-};
-
-Layout make_layout(const lbm_ltne_params* p, bool has_phi, bool has_hv) {
-  Layout L{};
-  const long long n = static_cast<long long>(p->nx) * p->ny;
-  L.pop_bytes = align_up(kPlanes * plane_elems(p->nx, p->ny) * storage_bytes(p->precision), kAlign);
-  L.field_bytes = align_up(n * compute_bytes(p->precision), kAlign);
-  L.mac_bytes = align_up(5 * n * compute_bytes(p->precision), kAlign);
-  size_t o = 0;
-  L.off_pop[0] = o; o += L.pop_bytes;
-  L.off_pop[1] = o; o += L.pop_bytes;
-  L.off_phi = o; o += has_phi ? L.field_bytes : 0;
-  L.off_hv = o; o += has_hv ? L.field_bytes : 0;
-  L.off_mac[0] = o; o += L.mac_bytes;
-  L.off_mac[1] = o; o += L.mac_bytes;
-  L.off_partial = o; o += align_up(kSumBlocks * kSums * sizeof(double), kAlign);
-  L.off_result = o; o += kAlign;
-  L.total = o;
-  return L;
-}
-
-TileMap make_tiles(int nx, int ny) {
-  TileMap t{};
-  t.tw_shift = nx >= 256 ? 8 : (nx >= 128 ? 7 : 6);
-  if (t.tw_shift > kTwShiftMax) t.tw_shift = kTwShiftMax;
-  const int tw = 1 << t.tw_shift, th = (kBlock / tw) * kRows;
-  t.ntx = (nx + tw - 1) / tw;
-  const int nty = (ny + th - 1) / th;
-  t.ntiles = t.ntx * nty;
-  t.per_xcd = (t.ntiles + kXcds - 1) / kXcds;
-  return t;
-}
-
-int grid_blocks(const TileMap& t) { return kXcdRemap ? kXcds * t.per_xcd : t.ntiles; }
-
-}  // namespace
 
 struct lbm_ltne {
   lbm_ltne_params p;
@@ -112,51 +44,7 @@ namespace {
 
 template <typename C>
 void fill_consts(const lbm_ltne* h, StepConsts<C>* k) {
-  const lbm_ltne_params& p = h->p;
-  const lbm_ltne_derived& d = h->d;
-  k->nx = p.nx;
-  k->ny = p.ny;
-  k->px = p.periodic_x;
-  k->py = p.periodic_y;
-  k->plane = plane_elems(p.nx, p.ny);
-  k->mplane = h->n();
-  k->tm = make_tiles(p.nx, p.ny);
-  k->rho0 = static_cast<C>(p.rho0);
-  k->phi_u = static_cast<C>(p.phi);
-  k->hv_u = static_cast<C>(p.Hv);
-  k->gbeta = static_cast<C>(d.gbeta);
-  k->dT0 = static_cast<C>(d.T_ref - p.T0);
-  k->Gbx = static_cast<C>(p.body_force[0]);
-  k->Gby = static_cast<C>(p.body_force[1]);
-  k->nu_over_K = static_cast<C>(d.nu_f / d.K);
-  k->inv_sqrtK = static_cast<C>(1.0 / std::sqrt(d.K));
-  k->Fphi = static_cast<C>(p.F_phi >= 0.0 ? p.F_phi : -1.0);
-  k->hvf = static_cast<C>(d.alpha_f / (d.L * d.L));
-  k->inv_sigma = static_cast<C>(1.0 / p.sigma);
-  k->Qf = static_cast<C>(p.Qf);
-  k->Qs = static_cast<C>(p.Qs);
-  k->s_e = static_cast<C>(p.s_e);
-  k->s_eps = static_cast<C>(p.s_eps);
-  k->s_q = static_cast<C>(p.s_q);
-  k->s_nu = static_cast<C>(d.s_nu);
-  k->z_a = static_cast<C>(d.zeta_a);
-  k->z_e = static_cast<C>(p.zeta_e);
-  k->z_nu = static_cast<C>(p.zeta_nu);
-  k->e_a = static_cast<C>(d.eta_a);
-  k->e_e = static_cast<C>(p.eta_e);
-  k->e_nu = static_cast<C>(p.eta_nu);
-  k->varpi = static_cast<C>(p.varpi);
-  k->T_ref = static_cast<C>(d.T_ref);
-  for (int w = 0; w < 4; ++w) {
-    k->wall_kind[w] = p.wall_thermal[w];
-    k->theta_wall[w] = static_cast<C>(p.T_wall[w] - d.T_ref);
-  }
-  k->sf = static_cast<C>(d.scale_f);
-  k->inv_sf = static_cast<C>(1.0 / d.scale_f);
-  k->sg = static_cast<C>(d.scale_g);
-  k->inv_sg = static_cast<C>(1.0 / d.scale_g);
-  k->theta_init_f = static_cast<C>(p.T_init_f - d.T_ref);
-  k->theta_init_s = static_cast<C>(p.T_init_s - d.T_ref);
+  fill_step_consts(h->p, h->d, k);
 }
 
 template <typename S, typename C, int F>
@@ -215,19 +103,6 @@ int upload_field(const lbm_ltne* h, const double* src, void* dst) {
     HIP_TRY(hipMemcpyAsync(dst, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));  // tmp goes out of scope
   }
-  return LBM_OK;
-}
-
-int check_device(int* dev) {
-  int count = 0;
-  if (hipGetDeviceCount(&count) != hipSuccess || count == 0)
-    return set_error(LBM_ENODEV, "no HIP device is visible");
-  HIP_TRY(hipGetDevice(dev));
-  hipDeviceProp_t prop;
-  HIP_TRY(hipGetDeviceProperties(&prop, *dev));
-  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-    return set_error(LBM_ENODEV, "device %d is %s; this library is built for gfx950", *dev,
-                     prop.gcnArchName);
   return LBM_OK;
 }
 

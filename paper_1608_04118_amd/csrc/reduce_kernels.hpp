@@ -57,8 +57,9 @@ __global__ __launch_bounds__(kBlock) void sums_kernel(const C* __restrict__ mac,
     for (int j = 0; j < kSums; ++j) partial[blockIdx.x * kSums + j] = v[j];
 }
 
-// Sums nparts partial rows into out[0..kSums) (one workgroup).
-__global__ __launch_bounds__(kBlock) void sums_final_kernel(const double* __restrict__ partial,
+// Sums nparts partial rows into out[0..kSums) (one workgroup).  Internal
+// linkage: every translation unit that launches it has its own copy.
+static __global__ __launch_bounds__(kBlock) void sums_final_kernel(const double* __restrict__ partial,
                                                             int nparts, double* __restrict__ out) {
   __shared__ double lds[kSums][kBlock];
   double v[kSums] = {0, 0, 0, 0, 0, 0, 0, 0};
