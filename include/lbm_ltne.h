@@ -203,6 +203,24 @@ size_t lbm_ltne_state_bytes(lbm_ltne_t h);
 int lbm_ltne_save(lbm_ltne_t h, void *host_buf, size_t bytes);
 int lbm_ltne_load(lbm_ltne_t h, const void *host_buf, size_t bytes);
 
+/*
+ * Discrete adjoint (reverse-time) of the time stepping.  Advances the lattice
+ * by nsteps >= 1 steps from its current state exactly as lbm_ltne_step does,
+ * and returns the loss L = mean hot-wall Nusselt number of the fluid phase
+ * (lbm_ltne_nusselt) at the final time, with dL/dphi and dL/dH_v at every
+ * node (host arrays of nx*ny doubles, row-major; either may be NULL).  The
+ * gradient is that of the discrete map actually computed: every step,
+ * the wall reconstruction and, when the handle is still at t = 0, the
+ * initialisation.  Checkpoints of the state are kept every ckpt_every steps
+ * (< 1: one segment) and each segment is recomputed once while its
+ * per-node sums are recorded.  Work memory of about
+ * (nsteps/ckpt_every + 2) state copies + 20 x ckpt_every bytes per node
+ * (binary32) is allocated for the call.  FP32 and FP64 forms only
+ * (LBM_EUNSUPPORTED for FP16 storage).  Synchronizes.
+ */
+int lbm_ltne_adjoint(lbm_ltne_t h, int64_t nsteps, int64_t ckpt_every, double *loss, double *dL_dphi,
+                     double *dL_dHv);
+
 /* Derived lattice values of a live handle. */
 int lbm_ltne_get_derived(lbm_ltne_t h, lbm_ltne_derived *d);
 

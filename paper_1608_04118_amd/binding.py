@@ -86,6 +86,7 @@ def lib():
             "lbm_ltne_macros": ([vp, vp, vp, vp, vp, vp], C.c_int),
             "lbm_ltne_nusselt": ([vp, dp, dp], C.c_int),
             "lbm_ltne_diagnostics": ([vp, dp, dp, dp], C.c_int),
+            "lbm_ltne_adjoint": ([vp, i64, i64, dp, vp, vp], C.c_int),
             "lbm_ltne_state_bytes": ([vp], sz),
             "lbm_ltne_save": ([vp, vp, sz], C.c_int),
             "lbm_ltne_load": ([vp, vp, sz], C.c_int),
@@ -226,6 +227,17 @@ def lbm_ltne_diagnostics(h):
     return m.value, e.value, r.value
 
 
+def lbm_ltne_adjoint(h, nx: int, ny: int, nsteps: int, ckpt_every: int = 0):
+    """Advances nsteps and returns (loss, dL/dphi, dL/dHv): loss is the mean
+    hot-wall Nu_f at the final time, gradients are (ny, nx) float64 arrays."""
+    loss = C.c_double()
+    gp = np.zeros((ny, nx))
+    gh = np.zeros((ny, nx))
+    _check(lib().lbm_ltne_adjoint(h, int(nsteps), int(ckpt_every), C.byref(loss), _ptr(gp), _ptr(gh)),
+           "lbm_ltne_adjoint")
+    return loss.value, gp, gh
+
+
 def lbm_ltne_state_bytes(h) -> int:
     return int(lib().lbm_ltne_state_bytes(h))
 
@@ -308,6 +320,11 @@ class Lattice:
 
     def diagnostics(self):
         return lbm_ltne_diagnostics(self.h)
+
+    def adjoint(self, nsteps: int, ckpt_every: int = 0):
+        """(loss, dL/dphi, dL/dHv) of the mean hot-wall Nu_f after nsteps more
+        steps; the lattice advances by nsteps."""
+        return lbm_ltne_adjoint(self.h, self.nx, self.ny, nsteps, ckpt_every)
 
     def save(self) -> bytearray:
         return lbm_ltne_save(self.h)

@@ -42,11 +42,20 @@ constexpr bool kNtLoad = LTNE_NT_LOAD != 0;
 constexpr bool kNtStore = LTNE_NT_STORE != 0;
 constexpr int kPlanePad = LTNE_PLANE_PAD;      // elements between the end of one plane and the next
 
+// Velocity components of Eq. 8 (D2Q9; the first five are the D2Q5 set).
+__host__ __device__ constexpr int vel_x(int i) {
+  return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int vel_y(int i) {
+  return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+}
+
 // Flags of the fused step kernel.
 constexpr int kPhiField = 1;  // per-node porosity
 constexpr int kHvField = 2;   // per-node interphase coefficient
 constexpr int kMacros = 4;    // write rho, u, T_f, T_s of this step
 constexpr int kInit = 8;      // build the t = 0 populations instead of streaming
+constexpr int kRecord = 16;   // write q = (rho - rho0, j_x, j_y, sum g_f, sum h) at interior nodes
 
 // Mapping of workgroups to lattice tiles.  A tile is tw x (kRows 256 / tw)
 // nodes, tiles are numbered row-major, and workgroup b runs tile

@@ -21,7 +21,7 @@ namespace ltne {
 
 constexpr size_t kAlign = 256;
 constexpr int kSumBlocks = 1024;
-constexpr uint32_t kStateMagic = 0x454e544cu;  // "LTNE"
+constexpr uint32_t kStateMagic = 0x484e544cu;  // "LTNH": f, g_f and h = g_s - g_f
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 

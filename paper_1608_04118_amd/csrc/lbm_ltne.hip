@@ -12,6 +12,7 @@
 #include "host_common.hpp"
 #include "params.hpp"
 #include "reduce_kernels.hpp"
+#include "adjoint_kernel.hpp"
 #include "step_kernel.hpp"
 
 using namespace ltne;
@@ -30,6 +31,7 @@ struct lbm_ltne {
   int64_t steps = 0;
   StepConsts<double> kd{};
   StepConsts<float> kf{};
+  std::vector<double> tf0, ts0;  // initial temperature fields (if given), for the adjoint
 
   void* pop(int i) const { return base + lay.off_pop[i]; }
   void* mac(int i) const { return base + lay.off_mac[i]; }
@@ -49,22 +51,49 @@ void fill_consts(const lbm_ltne* h, StepConsts<C>* k) {
 
 template <typename S, typename C, int F>
 hipError_t launch_one(const lbm_ltne* h, const StepConsts<C>& k, const void* src, void* dst,
-                      void* mac, const void* init_tf, const void* init_ts) {
+                      void* mac, const void* init_tf, const void* init_ts, void* rec = nullptr) {
   const dim3 grid(grid_blocks(k.tm)), block(kBlock);
   hipLaunchKernelGGL((step_kernel<S, C, F>), grid, block, 0, h->stream,
                      static_cast<const S*>(src), static_cast<S*>(dst),
                      static_cast<const C*>(h->phi()), static_cast<const C*>(h->hv()),
                      static_cast<C*>(mac), static_cast<const C*>(init_tf),
-                     static_cast<const C*>(init_ts), k);
+                     static_cast<const C*>(init_ts), k, static_cast<C*>(rec));
   return hipGetLastError();
 }
 
 // Dispatch over the field flags; mode: 0 plain step, 1 step writing macros,
-// 2 initialisation (writes macros).
+// 2 initialisation (writes macros), 3 step recording q at interior nodes,
+// 4 recording step that also writes macros (modes 3, 4: FP32 and FP64 only).
 template <typename S, typename C>
 hipError_t launch_step_t(const lbm_ltne* h, const StepConsts<C>& k, int mode, const void* src,
-                         void* dst, void* mac, const void* init_tf, const void* init_ts) {
+                         void* dst, void* mac, const void* init_tf, const void* init_ts,
+                         void* rec) {
   const int fl = (h->has_phi ? kPhiField : 0) | (h->has_hv ? kHvField : 0);
+  if constexpr (!std::is_same<S, _Float16>::value) {
+    if (mode == 3 || mode == 4) {
+      switch (fl) {
+        case 0:
+          return mode == 3 ? launch_one<S, C, kRecord>(h, k, src, dst, mac, init_tf, init_ts, rec)
+                           : launch_one<S, C, kRecord | kMacros>(h, k, src, dst, mac, init_tf, init_ts, rec);
+        case kPhiField:
+          return mode == 3 ? launch_one<S, C, kPhiField | kRecord>(h, k, src, dst, mac, init_tf, init_ts, rec)
+                           : launch_one<S, C, kPhiField | kRecord | kMacros>(h, k, src, dst, mac, init_tf,
+                                                                            init_ts, rec);
+        case kHvField:
+          return mode == 3 ? launch_one<S, C, kHvField | kRecord>(h, k, src, dst, mac, init_tf, init_ts, rec)
+                           : launch_one<S, C, kHvField | kRecord | kMacros>(h, k, src, dst, mac, init_tf,
+                                                                           init_ts, rec);
+        default:
+          return mode == 3
+                     ? launch_one<S, C, kPhiField | kHvField | kRecord>(h, k, src, dst, mac, init_tf, init_ts, rec)
+                     : launch_one<S, C, kPhiField | kHvField | kRecord | kMacros>(h, k, src, dst, mac, init_tf,
+                                                                                 init_ts, rec);
+      }
+    }
+  } else {
+    (void)rec;
+    if (mode == 3 || mode == 4) return hipErrorInvalidValue;
+  }
 #define LTNE_CASE(FL)                                                                               \
   case FL:                                                                                          \
     if (mode == 0) return launch_one<S, C, FL>(h, k, src, dst, mac, init_tf, init_ts);               \
@@ -81,14 +110,14 @@ hipError_t launch_step_t(const lbm_ltne* h, const StepConsts<C>& k, int mode, co
 }
 
 hipError_t launch_step(const lbm_ltne* h, int mode, const void* src, void* dst, void* mac,
-                       const void* init_tf, const void* init_ts) {
+                       const void* init_tf, const void* init_ts, void* rec = nullptr) {
   switch (h->p.precision) {
     case LBM_FP64:
-      return launch_step_t<double, double>(h, h->kd, mode, src, dst, mac, init_tf, init_ts);
+      return launch_step_t<double, double>(h, h->kd, mode, src, dst, mac, init_tf, init_ts, rec);
     case LBM_FP32:
-      return launch_step_t<float, float>(h, h->kf, mode, src, dst, mac, init_tf, init_ts);
+      return launch_step_t<float, float>(h, h->kf, mode, src, dst, mac, init_tf, init_ts, rec);
     default:
-      return launch_step_t<_Float16, float>(h, h->kf, mode, src, dst, mac, init_tf, init_ts);
+      return launch_step_t<_Float16, float>(h, h->kf, mode, src, dst, mac, init_tf, init_ts, rec);
   }
 }
 
@@ -165,6 +194,8 @@ int lbm_ltne_create(const lbm_ltne_params* p, const double* phi_field, const dou
   h->stream = static_cast<hipStream_t>(hip_stream);
   h->has_phi = phi_field != nullptr;
   h->has_hv = Hv_field != nullptr;
+  if (Tf_init) h->tf0.assign(Tf_init, Tf_init + n);
+  if (Ts_init) h->ts0.assign(Ts_init, Ts_init + n);
   h->lay = make_layout(p, h->has_phi, h->has_hv);
   if (device_pool) {
     if (pool_bytes < h->lay.total) {
@@ -403,6 +434,208 @@ int lbm_ltne_get_derived(lbm_ltne_t h, lbm_ltne_derived* d) {
   *d = h->d;
   return LBM_OK;
 }
+
+}  // extern "C"
+
+#ifndef LTNE_ADJ32_LAM
+#define LTNE_ADJ32_LAM float
+#endif
+#ifndef LTNE_ADJ32_MATH
+#define LTNE_ADJ32_MATH double
+#endif
+
+namespace {
+
+// dNu_f/dT_f at interior nodes.  Nu_f is the mean over the hot wall of
+// -dT/dn with dT/dn = (-3 T_0 + 4 T_1 - T_2)/2 (see lbm_ltne_nusselt); the
+// reported temperature of a wall node is its Dirichlet value (no
+// dependence) or, on an adiabatic wall, T_f of its inward neighbour.
+std::vector<double> nusselt_weights(const lbm_ltne* h, int w) {
+  const int nx = h->p.nx, ny = h->p.ny;
+  const long long n = h->n();
+  std::vector<double> wT(n, 0.0), wI(n, 0.0);
+  const int len = (w < 2) ? ny : nx;
+  const int periodic_t = (w < 2) ? h->p.periodic_y : h->p.periodic_x;
+  double W = 0.0;
+  for (int kk = 0; kk < len; ++kk) W += (!periodic_t && (kk == 0 || kk == len - 1)) ? 0.5 : 1.0;
+  const double scale = h->d.L / h->d.dT;
+  for (int kk = 0; kk < len; ++kk) {
+    long long i0, i1, i2;
+    if (w == 0) { i0 = 1LL * kk * nx; i1 = i0 + 1; i2 = i0 + 2; }
+    else if (w == 1) { i0 = 1LL * kk * nx + nx - 1; i1 = i0 - 1; i2 = i0 - 2; }
+    else if (w == 2) { i0 = kk; i1 = nx + kk; i2 = 2LL * nx + kk; }
+    else { i0 = 1LL * (ny - 1) * nx + kk; i1 = i0 - nx; i2 = i0 - 2LL * nx; }
+    const double c = ((!periodic_t && (kk == 0 || kk == len - 1)) ? 0.5 : 1.0) * scale / W;
+    wT[i0] += 1.5 * c;
+    wT[i1] += -2.0 * c;
+    wT[i2] += 0.5 * c;
+  }
+  for (long long i = 0; i < n; ++i) {
+    if (wT[i] == 0.0) continue;
+    const int x = static_cast<int>(i % nx), y = static_cast<int>(i / nx);
+    const bool wx = !h->p.periodic_x && (x == 0 || x == nx - 1);
+    const bool wy = !h->p.periodic_y && (y == 0 || y == ny - 1);
+    if (!wx && !wy) {
+      wI[i] += wT[i];
+      continue;
+    }
+    bool dirichlet = false;
+    if (wx && h->p.wall_thermal[x == 0 ? 0 : 1] == LBM_WALL_DIRICHLET) dirichlet = true;
+    if (!dirichlet && wy && h->p.wall_thermal[y == 0 ? 2 : 3] == LBM_WALL_DIRICHLET) dirichlet = true;
+    if (dirichlet) continue;
+    const int xf = wx ? (x == 0 ? 1 : nx - 2) : x;
+    const int yf = wy ? (y == 0 ? 1 : ny - 2) : y;
+    wI[1LL * yf * nx + xf] += wT[i];
+  }
+  return wI;
+}
+
+template <typename C>
+int upload_compute(const lbm_ltne* h, const std::vector<double>& src, void* dst) {
+  std::vector<C> tmp(src.size());
+  for (size_t i = 0; i < src.size(); ++i) tmp[i] = static_cast<C>(src[i]);
+  HIP_TRY(hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(C), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+// R: the lattice's compute type (fields, recorded sums); Lm: storage of the
+// adjoint populations; C: arithmetic of the adjoint sweep.
+template <typename R, typename Lm, typename C>
+int adjoint_t(lbm_ltne* h, int64_t nsteps, int64_t K, double* loss, double* dphi, double* dhv) {
+  const StepConsts<C>& k = *reinterpret_cast<const StepConsts<C>*>(
+      std::is_same<C, double>::value ? static_cast<const void*>(&h->kd) : static_cast<const void*>(&h->kf));
+  const long long n = h->n();
+  const int w = hot_wall(&h->p);
+  if (w < 0) return set_error(LBM_EINVAL, "no wall selected for the Nusselt number");
+  const bool include_init = (h->steps == 0);
+  const int64_t nseg = (nsteps + K - 1) / K;
+  const size_t popb = h->lay.pop_bytes;
+  const size_t recb = align_up(static_cast<size_t>(K) * 5 * n * sizeof(R), kAlign);
+  const size_t lamb = align_up(static_cast<size_t>(kPlanes) * k.plane * sizeof(Lm), kAlign);
+  const size_t gb = align_up(n * sizeof(double), kAlign);
+  const size_t fb = align_up(n * sizeof(R), kAlign);
+  const size_t total = nseg * popb + 2 * popb + recb + 2 * lamb + 2 * gb + 3 * fb;
+  char* buf = nullptr;
+  if (hipMalloc(&buf, total) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(LBM_ENOMEM, "adjoint work memory of %zu bytes failed", total);
+  }
+  char* ckpt = buf;
+  char* work[2] = {ckpt + nseg * popb, ckpt + nseg * popb + popb};
+  R* rec = reinterpret_cast<R*>(work[1] + popb);
+  Lm* lam[2] = {reinterpret_cast<Lm*>(reinterpret_cast<char*>(rec) + recb),
+                reinterpret_cast<Lm*>(reinterpret_cast<char*>(rec) + recb + lamb)};
+  double* gphi = reinterpret_cast<double*>(reinterpret_cast<char*>(lam[1]) + lamb);
+  double* ghv = reinterpret_cast<double*>(reinterpret_cast<char*>(gphi) + gb);
+  R* wseed = reinterpret_cast<R*>(reinterpret_cast<char*>(ghv) + gb);
+  R* itf = reinterpret_cast<R*>(reinterpret_cast<char*>(wseed) + fb);
+  R* its = reinterpret_cast<R*>(reinterpret_cast<char*>(itf) + fb);
+  auto fail = [&](int rc) {
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(buf);
+    return rc;
+  };
+  auto hip_fail = [&](hipError_t e, const char* what) {
+    return fail(set_error(LBM_EHIP, "adjoint %s: %s", what, hipGetErrorString(e)));
+  };
+  hipError_t e;
+  // forward with checkpoints; the handle itself advances to t0 + nsteps
+  for (int64_t sg = 0; sg < nseg; ++sg) {
+    e = hipMemcpyAsync(ckpt + sg * popb, h->pop(h->cur), popb, hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "checkpoint");
+    const int64_t steps_in = std::min<int64_t>(K, nsteps - sg * K);
+    for (int64_t j = 0; j < steps_in; ++j) {
+      e = launch_step(h, 0, h->pop(h->cur), h->pop(1 - h->cur), nullptr, nullptr, nullptr);
+      if (e != hipSuccess) return hip_fail(e, "forward launch");
+      h->cur = 1 - h->cur;
+    }
+  }
+  int rc = upload_compute<R>(h, nusselt_weights(h, w), wseed);
+  if (rc != LBM_OK) return fail(rc);
+  if ((e = hipMemsetAsync(gphi, 0, 2 * gb, h->stream)) != hipSuccess) return hip_fail(e, "zero");
+  const dim3 grid(grid_blocks(k.tm)), block(kBlock);
+  const R* phi = static_cast<const R*>(h->phi());
+  const R* hv = static_cast<const R*>(h->hv());
+  int la = 0;
+  for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+    // recompute the segment, recording q of every step
+    e = hipMemcpyAsync(work[0], ckpt + sg * popb, popb, hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "restore");
+    const int64_t steps_in = std::min<int64_t>(K, nsteps - sg * K);
+    int wc = 0;
+    for (int64_t j = 1; j <= steps_in; ++j) {
+      const bool last = (sg == nseg - 1 && j == steps_in);
+      e = launch_step(h, last ? 4 : 3, work[wc], work[1 - wc], last ? h->mac(1 - h->mcur) : nullptr,
+                      nullptr, nullptr, rec + (j - 1) * 5 * n);
+      if (e != hipSuccess) return hip_fail(e, "recompute launch");
+      wc = 1 - wc;
+    }
+    int64_t jhi = steps_in;
+    if (sg == nseg - 1) {
+      hipLaunchKernelGGL((adjoint_kernel<Lm, C, R, kAdjSeed>), grid, block, 0, h->stream, nullptr, lam[la],
+                         rec + (steps_in - 1) * 5 * n, phi, hv, gphi, ghv, wseed, nullptr, nullptr, k);
+      if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "seed launch");
+      jhi = steps_in - 1;
+    }
+    for (int64_t j = jhi; j >= 1; --j) {
+      hipLaunchKernelGGL((adjoint_kernel<Lm, C, R, kAdjStep>), grid, block, 0, h->stream, lam[la], lam[1 - la],
+                         rec + (j - 1) * 5 * n, phi, hv, gphi, ghv, nullptr, nullptr, nullptr, k);
+      if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "adjoint launch");
+      la = 1 - la;
+    }
+  }
+  if (include_init) {
+    const R* tf = nullptr;
+    const R* ts = nullptr;
+    if (!h->tf0.empty()) {
+      std::vector<double> rel(h->tf0);
+      for (auto& v : rel) v -= h->d.T_ref;
+      if ((rc = upload_compute<R>(h, rel, itf)) != LBM_OK) return fail(rc);
+      tf = itf;
+    }
+    if (!h->ts0.empty()) {
+      std::vector<double> rel(h->ts0);
+      for (auto& v : rel) v -= h->d.T_ref;
+      if ((rc = upload_compute<R>(h, rel, its)) != LBM_OK) return fail(rc);
+      ts = its;
+    }
+    hipLaunchKernelGGL((adjoint_kernel<Lm, C, R, kAdjInit>), grid, block, 0, h->stream, lam[la], nullptr, nullptr, phi,
+                       hv, gphi, ghv, nullptr, tf, ts, k);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "init adjoint launch");
+  }
+  h->mcur = 1 - h->mcur;
+  h->steps += nsteps;
+  if (dphi && (e = hipMemcpyAsync(dphi, gphi, n * sizeof(double), hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+    return hip_fail(e, "gradient copy");
+  if (dhv && (e = hipMemcpyAsync(dhv, ghv, n * sizeof(double), hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+    return hip_fail(e, "gradient copy");
+  if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(e, "sync");
+  (void)hipFree(buf);
+  if (loss) {
+    double nus = 0.0;
+    rc = lbm_ltne_nusselt(h, loss, &nus);
+    if (rc != LBM_OK) return rc;
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" int lbm_ltne_adjoint(lbm_ltne_t h, int64_t nsteps, int64_t ckpt_every, double* loss,
+                                double* dL_dphi, double* dL_dHv) {
+  if (!h) return set_error(LBM_EINVAL, "handle is NULL");
+  if (nsteps < 1) return set_error(LBM_EINVAL, "nsteps = %lld must be >= 1", static_cast<long long>(nsteps));
+  if (ckpt_every < 1) ckpt_every = nsteps;
+  if (ckpt_every > nsteps) ckpt_every = nsteps;
+  if (h->p.precision == LBM_FP16S)
+    return set_error(LBM_EUNSUPPORTED, "the adjoint is built for the FP32 and FP64 forms");
+  if (h->p.precision == LBM_FP64)
+    return adjoint_t<double, double, double>(h, nsteps, ckpt_every, loss, dL_dphi, dL_dHv);
+  return adjoint_t<float, LTNE_ADJ32_LAM, LTNE_ADJ32_MATH>(h, nsteps, ckpt_every, loss, dL_dphi, dL_dHv);
+}
+
+extern "C" {
 
 int lbm_ltne_destroy(lbm_ltne_t h) {
   if (!h) return LBM_OK;

@@ -107,7 +107,8 @@ template <typename S, typename C, int F>
 __device__ __forceinline__ void node_update(
     const int x, const int y, const S* __restrict__ src, S* __restrict__ dst,
     const C* __restrict__ phi_field, const C* __restrict__ hv_field, C* __restrict__ mac,
-    const C* __restrict__ init_tf, const C* __restrict__ init_ts, const StepConsts<C>& k) {
+    const C* __restrict__ init_tf, const C* __restrict__ init_ts, const StepConsts<C>& k,
+    C* __restrict__ rec = nullptr) {
   const int nx = k.nx, ny = k.ny;
 
   // Wall classification and the node whose post-streaming populations this
@@ -124,7 +125,7 @@ __device__ __forceinline__ void node_update(
 
   C f0, f1, f2, f3, f4, f5, f6, f7, f8;
   C a0, a1, a2, a3, a4;  // fluid temperature populations
-  C b0, b1, b2, b3, b4;  // solid temperature populations
+  C b0, b1, b2, b3, b4;  // solid minus fluid temperature populations
   if constexpr ((F & kInit) != 0) {
     // t = 0: fluid at rest at rho0 (all shifted D2Q9 populations vanish) and
     // g = w~ (T - Sr / 2), so that Eqs. 43-44 give back the initial T.
@@ -137,11 +138,12 @@ __device__ __forceinline__ void node_update(
     const C srs = C(2) * d1 * (thf - ths) + k.Qs;
     const C w0 = C(1) - k.varpi, w1 = C(0.25) * k.varpi;
     f0 = f1 = f2 = f3 = f4 = f5 = f6 = f7 = f8 = C(0);
-    const C gf = thf - C(0.5) * srf, gs = ths - C(0.5) * srs;
+    const C gf = thf - C(0.5) * srf;
+    const C gh = (ths - thf) - C(0.5) * (srs - srf);
     a0 = w0 * gf;
     a1 = a2 = a3 = a4 = w1 * gf;
-    b0 = w0 * gs;
-    b1 = b2 = b3 = b4 = w1 * gs;
+    b0 = w0 * gh;
+    b1 = b2 = b3 = b4 = w1 * gh;
   } else {
     // Pull: population i arrives from node (xc, yc) - e_i.
     int xm = xc - 1, xp = xc + 1, ym = yc - 1, yp = yc + 1;
@@ -178,28 +180,42 @@ __device__ __forceinline__ void node_update(
   }
 
   // ---- macros at (xc, yc) ----
-  // Temperatures, Eqs. 43-46, relative to T_ref.  Written as
-  //   T_f = A + d0 D,  T_s = B - d1 D,  D = T_s - T_f = (B - A) / (1 + d0 + d1),
-  // which equals Eqs. 43-44 and keeps every rounding on the small
-  // correction, so the carried sums A, B are never scaled by a rounded
-  // factor close to 1 (a systematic drift in binary32 otherwise).
+  // Temperatures, Eqs. 43-46, relative to T_ref.  The solid lattice is
+  // carried as its difference from the fluid one, so its zeroth moment is
+  // sum g_s - sum g_f directly and
+  //   D = T_s - T_f = (B - A) / (1 + d0 + d1),  T_f = A + d0 D,  T_s = T_f + D,
+  // which equals Eqs. 43-44.  The interphase exchange of one step, 2 d0 D,
+  // can be far below the rounding unit of the temperature populations
+  // themselves; on the difference lattice it is resolved to full relative
+  // precision, and no carried sum is ever scaled by a rounded factor close
+  // to 1 (a systematic drift in binary32 otherwise).
   C hv = hv_c * k.hvf;  // h_v / (rho c_p)_f
   const C rphi_c = dev_rcp(phi_c);
   C d0 = C(0.5) * hv * rphi_c;
   C d1 = C(0.5) * hv * k.inv_sigma * dev_rcp(C(1) - phi_c);
   const C sgf = ((a0 + a1) + (a2 + a3)) + a4;
-  const C sgs = ((b0 + b1) + (b2 + b3)) + b4;
+  const C sgh = ((b0 + b1) + (b2 + b3)) + b4;  // sum g_s - sum g_f
   const C A = sgf + C(0.5) * k.Qf;
-  const C B = sgs + C(0.5) * k.Qs;
-  const C D = (B - A) * dev_rcp(C(1) + d0 + d1);
+  C D = (sgh + C(0.5) * (k.Qs - k.Qf)) * dev_rcp(C(1) + d0 + d1);
   C thf = A + d0 * D;
-  C ths = B - d1 * D;
+  C ths = thf + D;
 
   // Density (Eq. 18) and momentum sums.
   const C drho = ((f0 + f1) + (f2 + f3)) + ((f4 + f5) + (f6 + f7)) + f8;
   const C rho = k.rho0 + drho;
   const C jx = (f1 - f3) + (f5 - f6) + (f8 - f7);
   const C jy = (f2 - f4) + (f5 + f6) - (f7 + f8);
+
+  if constexpr ((F & kRecord) != 0) {
+    if (!wall) {
+      const int ir = y * nx + x;
+      rec[0 * k.mplane + ir] = drho;
+      rec[1 * k.mplane + ir] = jx;
+      rec[2 * k.mplane + ir] = jy;
+      rec[3 * k.mplane + ir] = sgf;
+      rec[4 * k.mplane + ir] = sgh;
+    }
+  }
 
   // Buoyancy (Eq. 6, gravity along -y) plus body acceleration.
   const C Gx = k.Gbx;
@@ -226,21 +242,24 @@ __device__ __forceinline__ void node_update(
   }
   // Post-collision conserved moments.  In the interior, Eq. 19 gives
   // rho u + rho F / 2 = j + rho F (momentum plus the force of one step) and
-  // the zeroth thermal moments gain the source: n_0* = n_0 + Sr.
+  // the zeroth thermal moments gain the source: n_0* = n_0 + Sr (for the
+  // difference lattice: Sr_s - Sr_f = Q_s - Q_f - 2 (d0 + d1) D).
   C ms3 = jx + rFx, ms5 = jy + rFy;
   C srf = C(2) * d0 * D + k.Qf;  // Eq. 42
   C srs = C(-2) * d1 * D + k.Qs;
-  C nf0 = sgf + srf, nsol0 = sgs + srs;
+  C dsr = (k.Qs - k.Qf) - C(2) * (d0 + d1) * D;  // Sr_s - Sr_f
+  C nf0 = sgf + srf, nh0 = sgh + dsr;
 
   C phi = phi_c;
   C rphi = rphi_c;
   if (wall) {
     // Non-equilibrium extrapolation from the inward neighbour:
     //   f(x_b) = f^eq(rho, 0) + f(x_f) - f^eq(rho, u),
-    //   g_f(x_b) = g_f^eq(T_b, 0) + g_f(x_f) - g_f^eq(T_f, u), g_s likewise.
+    //   g_f(x_b) = g_f^eq(T_b, 0) + g_f(x_f) - g_f^eq(T_f, u), g_s likewise
+    // (the difference lattice takes the difference of the two).
     C thfb = thf, thsb = ths;
+    int kind = 1;
     {
-      int kind = 1;
       C tw = C(0);
       if (wx) {
         const int w = (x == 0) ? 0 : 1;
@@ -252,6 +271,8 @@ __device__ __forceinline__ void node_update(
       }
       if (kind == 0) thfb = thsb = tw;
     }
+    // T_s - T_f at the wall: zero on a Dirichlet wall, D of x_f otherwise
+    const C Db = (kind == 0) ? C(0) : D;
     const C ip = rphi_c;
     const C uu = (ux * ux + uy * uy) * ip;
     const C r9 = rho * (C(1) / C(9)), r36 = rho * (C(1) / C(36));
@@ -268,18 +289,18 @@ __device__ __forceinline__ void node_update(
     f8 -= r36 * (C(3) * sm + C(4.5) * sm * sm * ip - q0);
     f6 -= r36 * (-C(3) * sm + C(4.5) * sm * sm * ip - q0);
     const C w0 = C(1) - k.varpi, w1 = C(0.25) * k.varpi;
-    const C dtf = thfb - thf, dts = thsb - ths;
+    const C dtf = thfb - thf, dD = Db - D;
     const C adv = C(0.5) * (thf + k.T_ref) * ip;  // (e.u) T_f / (2 phi)
     a0 += w0 * dtf;
     a1 += w1 * dtf - adv * ux;
     a3 += w1 * dtf + adv * ux;
     a2 += w1 * dtf - adv * uy;
     a4 += w1 * dtf + adv * uy;
-    b0 += w0 * dts;
-    b1 += w1 * dts;
-    b2 += w1 * dts;
-    b3 += w1 * dts;
-    b4 += w1 * dts;
+    b0 += w0 * dD;
+    b1 += w1 * dD + adv * ux;
+    b3 += w1 * dD - adv * ux;
+    b2 += w1 * dD + adv * uy;
+    b4 += w1 * dD - adv * uy;
     // Prescribed wall values; coefficients at the wall node itself.
     const int ib = y * nx + x;
     phi = (F & kPhiField) ? phi_field[ib] : k.phi_u;
@@ -289,6 +310,7 @@ __device__ __forceinline__ void node_update(
     d1 = C(0.5) * hvb * k.inv_sigma * dev_rcp(C(1) - phi);
     thf = thfb;
     ths = thsb;
+    D = Db;
     Gy = k.Gby + k.gbeta * (thf + k.dT0);
     ux = C(0);
     uy = C(0);
@@ -296,10 +318,11 @@ __device__ __forceinline__ void node_update(
     rFy = rho * phi * Gy;
     ms3 = C(0.5) * rFx;  // rho u + rho F / 2 with u = 0
     ms5 = C(0.5) * rFy;
-    srf = C(2) * d0 * (ths - thf) + k.Qf;
-    srs = C(2) * d1 * (thf - ths) + k.Qs;
+    srf = C(2) * d0 * D + k.Qf;
+    srs = C(-2) * d1 * D + k.Qs;
+    dsr = (k.Qs - k.Qf) - C(2) * (d0 + d1) * D;
     nf0 = thf + C(0.5) * srf;  // n_0* = T + Sr / 2 (Eq. 41 at the wall)
-    nsol0 = ths + C(0.5) * srs;
+    nh0 = D + C(0.5) * dsr;
   }
 
   if constexpr ((F & kMacros) != 0) {
@@ -410,22 +433,32 @@ __device__ __forceinline__ void node_update(
       store_pop(at(dst + 12 * P, io), r3, sg);
       store_pop(at(dst + 13 * P, io), r4, sg);
     }
-    // solid phase, equilibria of Eq. 38
+    // solid phase (Eq. 33, equilibria of Eq. 38), carried as the difference
+    // g_s - g_f: in moments, n_h* = n_s* - n_f* with n_s = n_f + n_h,
+    //   n_h1* = (1 - eta_a) n_h1 + (zeta_a - eta_a) n_f1 - zeta_a u_x T_f / phi,
+    //   n_h3* = (1 - eta_e) n_h3 + (zeta_e - eta_e)(n_f3 - c1 T_f) + c1 eta_e D
+    //           + c1 [(1 - eta_e / 2) Sr_s - (1 - zeta_e / 2) Sr_f],
+    //   n_h4* = (1 - eta_nu) n_h4 + (zeta_nu - eta_nu) n_f4,
+    // every term small where the two phases are close.
     {
+      const C nf1 = a1 - a3, nf2 = a2 - a4;
+      const C nf3 = C(-4) * a0 + ((a1 + a2) + (a3 + a4));
+      const C nf4 = (a1 - a2) + (a3 - a4);
       const C n1 = b1 - b3, n2 = b2 - b4;
       const C n3 = C(-4) * b0 + ((b1 + b2) + (b3 + b4));
       const C n4 = (b1 - b2) + (b3 - b4);
-      const C ns1 = n1 - k.e_a * n1;
-      const C ns2 = n2 - k.e_a * n2;
-      const C ns3 = n3 - k.e_e * (n3 - c1 * ths) + (C(1) - C(0.5) * k.e_e) * c1 * srs;
-      const C ns4 = n4 - k.e_nu * n4;
-      const C o0 = nsol0 * C(0.2);
+      const C ns1 = (C(1) - k.e_a) * n1 + ((k.z_a - k.e_a) * nf1 - k.z_a * ux * Tf * ip);
+      const C ns2 = (C(1) - k.e_a) * n2 + ((k.z_a - k.e_a) * nf2 - k.z_a * uy * Tf * ip);
+      const C ns3 = (C(1) - k.e_e) * n3 + (k.z_e - k.e_e) * (nf3 - c1 * thf) +
+                    c1 * (k.e_e * D + ((C(1) - C(0.5) * k.e_e) * srs - (C(1) - C(0.5) * k.z_e) * srf));
+      const C ns4 = (C(1) - k.e_nu) * n4 + (k.z_nu - k.e_nu) * nf4;
+      const C o0 = nh0 * C(0.2);
       const C o3 = ns3 * C(0.05);
       const C o4 = ns4 * C(0.25);
       const C h1 = ns1 * C(0.5), h2 = ns2 * C(0.5);
       const C r1 = o0 + h1 + o3 + o4, r2 = o0 + h2 + o3 - o4;
       const C r3 = o0 - h1 + o3 + o4, r4 = o0 - h2 + o3 - o4;
-      store_pop(at(dst + 14 * P, io), nsol0 - ((r1 + r2) + (r3 + r4)), sg);
+      store_pop(at(dst + 14 * P, io), nh0 - ((r1 + r2) + (r3 + r4)), sg);
       store_pop(at(dst + 15 * P, io), r1, sg);
       store_pop(at(dst + 16 * P, io), r2, sg);
       store_pop(at(dst + 17 * P, io), r3, sg);
@@ -440,7 +473,7 @@ template <typename S, typename C, int F>
 __global__ __launch_bounds__(kBlock) void step_kernel(
     const S* __restrict__ src, S* __restrict__ dst, const C* __restrict__ phi_field,
     const C* __restrict__ hv_field, C* __restrict__ mac, const C* __restrict__ init_tf,
-    const C* __restrict__ init_ts, const StepConsts<C> k) {
+    const C* __restrict__ init_ts, const StepConsts<C> k, C* __restrict__ rec = nullptr) {
   const int b = blockIdx.x;
   const int t = kXcdRemap ? (b & (kXcds - 1)) * k.tm.per_xcd + (b >> 3) : b;
   if (t >= k.tm.ntiles) return;
@@ -454,7 +487,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(
 #pragma unroll
   for (int r = 0; r < kRows; ++r) {
     const int y = y0 + r * th;
-    if (y < k.ny) node_update<S, C, F>(x, y, src, dst, phi_field, hv_field, mac, init_tf, init_ts, k);
+    if (y < k.ny) node_update<S, C, F>(x, y, src, dst, phi_field, hv_field, mac, init_tf, init_ts, k, rec);
   }
 }
 

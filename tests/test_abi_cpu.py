@@ -127,3 +127,10 @@ def test_create_rejects_before_touching_a_device(lib):
     with pytest.raises(B.LtneError) as e:
         B.lbm_ltne_create(I.cavity_small(), phi_field=bad_phi)
     assert e.value.code in (B.LBM_EINVAL, B.LBM_ENODEV)
+
+
+def test_null_handles_are_refused(lib):
+    L = B.lib()
+    assert L.lbm_ltne_step(None, 1) == B.LBM_EINVAL
+    assert L.lbm_ltne_adjoint(None, 10, 0, None, None, None) == B.LBM_EINVAL
+    assert L.lbm_ltne_destroy(None) in (B.LBM_OK, B.LBM_EINVAL)

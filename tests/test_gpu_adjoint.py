@@ -1,0 +1,188 @@
+"""Discrete adjoint on the GPU: gradients of the mean hot-wall Nusselt number
+with respect to the per-node porosity and interphase coefficient.
+
+FP64: equal to reverse-mode differentiation of the oracle's transcription
+(binary64, CPU) within 1e-10 of the gradient scale.  FP32 at 512^2 over 4000
+steps with checkpoints every 200: equal to central differences of the FP64
+forward within 1e-4 of the largest difference over 32 seeded interior cells.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_1608_04118_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-adjoint]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_1608_04118_amd import binding
+    binding.lib()
+    return binding
+
+
+def _fields(nx, ny, seed):
+    r = np.random.default_rng(seed)
+    phi = np.clip(0.55 + 0.06 * r.standard_normal((ny, nx)), 0.4, 0.75)
+    Hv = 40.0 * (1 + 0.4 * r.uniform(-1, 1, (ny, nx)))
+    return phi, Hv
+
+
+def _small(kind, precision=I.FP64):
+    """Small lattices spanning several tiles with ragged edges."""
+    if kind == "cavity":
+        nx, ny = 70, 24
+        p = I.cavity_small(nx=nx, ny=ny, precision=precision, Ra=3e4, Da=3e-3, Hv=40.0, gamma_sf=3.0,
+                           sigma=1.5, Qf=1e-6, Qs=-1e-6)
+        extra = {}
+    elif kind == "periodic":
+        nx, ny = 40, 22
+        p = I.complete(nx=nx, ny=ny, precision=precision, periodic_x=1, wall_thermal=(1, 1, 0, 0),
+                       T_wall=(0, 0, 1.0, 0), T0=0.0, Ra=2e4, Da=1e-2, phi=0.55, F_phi=0.1, Hv=40.0,
+                       gamma_sf=2.0, sigma=1.2)
+        extra = {}
+    else:  # initial temperature fields, cold-wall Nusselt number, adiabatic left wall,
+        # unequal fluid / solid relaxation rates
+        nx, ny = 33, 30
+        p = I.cavity_small(nx=nx, ny=ny, precision=precision, Ra=2e4, Da=1e-2, Hv=40.0,
+                           wall_thermal=(1, 0, 0, 1), T_wall=(0, 0.0, 1.0, 0), nu_wall=1,
+                           eta_e=1.3, eta_nu=0.9, zeta_nu=1.2, gamma_sf=2.5)
+        r = np.random.default_rng(11)
+        extra = dict(Tf0=0.3 + 0.2 * r.uniform(size=(ny, nx)), Ts0=0.3 + 0.2 * r.uniform(size=(ny, nx)))
+    phi, Hv = _fields(nx, ny, 3)
+    return p, phi, Hv, extra
+
+
+@pytest.mark.parametrize("kind", ["cavity", "periodic", "init"])
+def test_fp64_adjoint_equals_autograd(B, kind):
+    from oracle import autograd as AG
+    import oracle as O
+    p, phi, Hv, extra = _small(kind)
+    n = 240
+    say(kind, "nx", p["nx"], "ny", p["ny"], "steps", n)
+    lat = B.Lattice(p, phi=phi, Hv=Hv, **extra)
+    loss, gp, gh = lat.adjoint(n, ckpt_every=50)
+    assert lat.steps == n
+    lo, ap, ah = AG.gradients(p, n, phi, Hv, extra.get("Tf0"), extra.get("Ts0"))
+    nu_o = O.Oracle(p, phi=phi, Hv=Hv, **extra).step(n).nusselt()[0]
+    ep = np.abs(gp - ap).max() / np.abs(ap).max()
+    eh = np.abs(gh - ah).max() / np.abs(ah).max()
+    say(kind, "loss %.15g oracle %.15g" % (loss, nu_o), "grad errors phi %.2e Hv %.2e" % (ep, eh))
+    assert abs(loss - nu_o) <= 1e-12 * abs(nu_o)
+    assert ep <= 1e-10 and eh <= 1e-10
+    lat.close()
+
+
+def test_checkpoint_spacing_and_state(B):
+    """Checkpoint spacing changes nothing (bitwise); the lattice ends where
+    plain stepping ends, with the same macros and Nusselt number."""
+    p, phi, Hv, _ = _small("cavity", I.FP32)
+    n = 97
+    out = []
+    for k in (0, 1, 13, 97, 500):
+        lat = B.Lattice(p, phi=phi, Hv=Hv)
+        out.append(lat.adjoint(n, ckpt_every=k))
+        if k == 13:
+            ref = B.Lattice(p, phi=phi, Hv=Hv).step(n)
+            a, b = lat.macros(), ref.macros()
+            for f in a:
+                assert np.array_equal(a[f], b[f]), f
+            assert lat.steps == n and lat.nusselt() == ref.nusselt()
+            assert out[-1][0] == ref.nusselt()[0]
+    for o in out[1:]:
+        assert o[0] == out[0][0]
+        assert np.array_equal(o[1], out[0][1]) and np.array_equal(o[2], out[0][2])
+
+
+def test_adjoint_from_a_given_state(B):
+    """After t0 steps the adjoint treats the state as an input."""
+    from oracle import autograd as AG
+    p, phi, Hv, _ = _small("cavity")
+    t0, n = 60, 120
+    lat = B.Lattice(p, phi=phi, Hv=Hv).step(t0)
+    loss, gp, gh = lat.adjoint(n, ckpt_every=40)
+    lo, ap, ah = AG.gradients(p, n, phi, Hv, t0=t0)
+    ep = np.abs(gp - ap).max() / np.abs(ap).max()
+    eh = np.abs(gh - ah).max() / np.abs(ah).max()
+    say("t0", t0, "errors %.2e %.2e" % (ep, eh))
+    assert abs(loss - lo) <= 1e-12 * abs(lo)
+    assert ep <= 1e-10 and eh <= 1e-10
+
+
+def test_fp32_adjoint_tracks_fp64(B):
+    p64, phi, Hv, _ = _small("cavity")
+    p32 = dict(p64, precision=I.FP32)
+    _, g64p, g64h = B.Lattice(p64, phi=phi, Hv=Hv).adjoint(400, 100)
+    _, g32p, g32h = B.Lattice(p32, phi=phi, Hv=Hv).adjoint(400, 100)
+    ep = np.abs(g32p - g64p).max() / np.abs(g64p).max()
+    eh = np.abs(g32h - g64h).max() / np.abs(g64h).max()
+    say("fp32 vs fp64 adjoint: phi %.2e Hv %.2e" % (ep, eh))
+    assert ep <= 1e-4 and eh <= 1e-4
+
+
+def test_fp16_storage_is_refused(B):
+    p = I.cavity_small(precision=I.FP16S)
+    lat = B.Lattice(p)
+    with pytest.raises(B.LtneError) as e:
+        lat.adjoint(10)
+    assert e.value.code == B.LBM_EUNSUPPORTED
+    assert lat.steps == 0
+
+
+def test_512_fp32_adjoint_vs_finite_differences(B):
+    """512^2 cavity, FP32, 4000 steps, checkpoints every 200: dL/dphi and
+    dL/dHv at 32 seeded interior cells against central differences of the
+    FP64 forward (steps 1e-3 and 1e-3 Hv, repeated with half steps)."""
+    import torch
+    n_side, n = 512, 4000
+    p32, phi, Hv = I.adjoint_cavity(n_side, precision=I.FP32)
+    p64 = dict(p32, precision=I.FP64)
+    cells = I.fd_cells(n_side)
+    lat = B.Lattice(p32, phi=phi, Hv=Hv)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    loss, gp, gh = lat.adjoint(n, ckpt_every=200)
+    t_adj = time.perf_counter() - t
+    fwd = B.Lattice(p32, phi=phi, Hv=Hv)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    fwd.step(n)
+    nu_fwd = fwd.nusselt()[0]
+    t_fwd = time.perf_counter() - t
+    say("512^2 fp32: loss %.10g forward Nu %.10g adjoint %.3f s forward %.3f s ratio %.2f"
+        % (loss, nu_fwd, t_adj, t_fwd, t_adj / t_fwd))
+    assert loss == nu_fwd
+
+    def L64(field, cell, h):
+        a = {"phi": phi, "Hv": Hv}
+        vals = []
+        for s in (1, -1):
+            f = a[field].copy()
+            f[cell] += s * h
+            kw = dict(a)
+            kw[field] = f
+            lt = B.Lattice(p64, phi=kw["phi"], Hv=kw["Hv"]).step(n)
+            vals.append(lt.nusselt()[0])
+            lt.close()
+        return (vals[0] - vals[1]) / (2 * h)
+
+    for field, g, hs in (("phi", gp, lambda c: 1e-3), ("Hv", gh, lambda c: 1e-3 * Hv[c])):
+        fd = np.array([L64(field, c, hs(c)) for c in cells])
+        fd2 = np.array([L64(field, c, 0.5 * hs(c)) for c in cells])
+        ad = np.array([g[c] for c in cells])
+        scale = np.abs(fd).max()
+        err = np.abs(ad - fd).max() / scale
+        cons = np.abs(fd - fd2).max() / scale
+        say(field, "max|g_FD| %.3e" % scale, "adjoint vs FD %.2e" % err, "FD h vs h/2 %.2e" % cons)
+        assert cons <= 1e-4
+        assert err <= 1e-4
