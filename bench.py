@@ -41,7 +41,8 @@ WORKLOAD = ("porous layer 8192x8192, periodic x, walls y (bottom T=1, top T=0), 
 BYTES_PER_LUP = {"f32": 19 * 4 * 2 + 4, "f64": 19 * 8 * 2 + 8, "f16s": 19 * 2 * 2 + 4}
 PRECISION = {"f32": 1, "f64": 0, "f16s": 2}
 KERNEL_SOURCES = ["paper_1608_04118_amd/csrc/step_kernel.hpp", "paper_1608_04118_amd/csrc/common.hpp",
-                  "paper_1608_04118_amd/csrc/lbm_ltne.hip"]
+                  "paper_1608_04118_amd/csrc/host_common.hpp", "paper_1608_04118_amd/csrc/lbm_ltne.hip",
+                  "paper_1608_04118_amd/build.py"]
 
 
 def kernel_hash() -> str:
@@ -138,6 +139,40 @@ def time_batch(steps: int, warmup: int, autotune: bool = True):
                 autotune_ms=tuned_ms)
 
 
+ADJ_WORKLOAD = ("adjoint: 512x512 cavity, FP32, per-node porosity clip(0.65+0.1 z_a, 0.4, 0.9) and "
+                "interphase coefficient 10 (1 + 0.5 clip(z_b, -1, 1)), Ra=1e5, Da=1e-3, loss = mean hot-wall "
+                "Nu_f after 4000 steps, checkpoints every 200")
+
+
+def time_adjoint(n_side: int = 512, steps: int = 4000, ckpt: int = 200):
+    """Cost of the gradient: lbm_ltne_adjoint over `steps` steps (its own
+    forward with checkpoints, the per-segment recompute and the reverse
+    sweep) against the plain forward of the same steps, both wall-clock
+    around synchronizing calls from a fresh lattice."""
+    import torch
+    from paper_1608_04118_amd import binding as B
+    from paper_1608_04118_amd import inputs as I
+    p, phi, Hv = I.adjoint_cavity(n_side, precision=I.FP32)
+    B.Lattice(p, phi=phi, Hv=Hv).adjoint(20, 10)  # loads the kernels
+    fwd = B.Lattice(p, phi=phi, Hv=Hv)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    fwd.step(steps)
+    nu = fwd.nusselt()[0]  # synchronizes
+    t_fwd = time.perf_counter() - t
+    lat = B.Lattice(p, phi=phi, Hv=Hv)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    loss, gp, gh = lat.adjoint(steps, ckpt)
+    t_adj = time.perf_counter() - t
+    if loss != nu or not (np.isfinite(gp).all() and np.isfinite(gh).all()):
+        raise RuntimeError("adjoint run inconsistent with the forward")
+    return {"workload": ADJ_WORKLOAD, "forward_ms": round(t_fwd * 1e3, 2), "adjoint_ms": round(t_adj * 1e3, 2),
+            "cost_ratio": round((t_adj - t_fwd) / t_fwd, 3), "cost_ratio_with_forward": round(t_adj / t_fwd, 3),
+            "note": "cost_ratio = (adjoint call - forward) / forward: recompute + reverse sweep per forward; "
+                    "the adjoint call also runs the forward itself"}
+
+
 def copy_bandwidth(gib: float = 1.0, reps: int = 5):
     """Plain device copy of a known size (torch's copy kernel): the
     reference kernel for the rocprofv3 byte counters, and a practical
@@ -228,6 +263,9 @@ def main():
     ap.add_argument("--forms", default="f32,f64,f16s")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-cavity batch workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the adjoint cost measurement (one JSON object)")
     ap.add_argument("--copy-check", action="store_true",
                     help="also time a plain 1 GiB device copy (reference for the byte counters)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -246,6 +284,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs an MI355X GPU", file=sys.stderr)
         sys.exit(2)
+    if args.adjoint_only:
+        print(json.dumps(time_adjoint()), flush=True)
+        return
     from paper_1608_04118_amd import inputs as I
     inputs = I.throughput(n=N, precision=I.FP32)
     forms = [f for f in args.forms.split(",") if f]
@@ -263,6 +304,12 @@ def main():
         batch = time_batch(args.steps, args.warmup)
         print("[bench] batch: %.3f ms/step, %.0f MLUPS, %.0f GB/s" % (
             batch["ms_per_step"], batch["mlups"], batch["achieved_gbs"]), file=sys.stderr, flush=True)
+    adjoint = None
+    if not args.no_adjoint:
+        print("[bench] timing the adjoint (512^2 FP32, 4000 steps)", file=sys.stderr, flush=True)
+        adjoint = time_adjoint()
+        print("[bench] adjoint: %.1f ms vs forward %.1f ms, cost ratio %.2f" % (
+            adjoint["adjoint_ms"], adjoint["forward_ms"], adjoint["cost_ratio"]), file=sys.stderr, flush=True)
     copy = None
     if args.copy_check:
         print("[bench] timing a plain 1 GiB device copy", file=sys.stderr, flush=True)
@@ -297,6 +344,7 @@ def main():
         "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                          for kk, vv in v.items()} for k, v in res.items()},
         "batch256_f32": batch,
+        "adjoint": adjoint,
     }
     print(json.dumps(out), flush=True)
 

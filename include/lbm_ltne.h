@@ -216,7 +216,8 @@ int lbm_ltne_load(lbm_ltne_t h, const void *host_buf, size_t bytes);
  * per-node sums are recorded.  Work memory of about
  * (nsteps/ckpt_every + 2) state copies + 20 x ckpt_every bytes per node
  * (binary32) is allocated for the call.  FP32 and FP64 forms only
- * (LBM_EUNSUPPORTED for FP16 storage).  Synchronizes.
+ * (LBM_EUNSUPPORTED for FP16 storage).  Synchronizes.  On an error the
+ * lattice is left at its state on entry (unless the device itself failed).
  */
 int lbm_ltne_adjoint(lbm_ltne_t h, int64_t nsteps, int64_t ckpt_every, double *loss, double *dL_dphi,
                      double *dL_dHv);

@@ -7,4 +7,4 @@
 * ``build``    -- hipcc build of the library for gfx950.
 """
 from . import binding, inputs  # noqa: F401
-from .binding import Lattice, LtneError  # noqa: F401
+from .binding import Lattice, LtneError, nusselt_loss  # noqa: F401

@@ -349,6 +349,52 @@ class Lattice:
             pass
 
 
+# --- autograd ---------------------------------------------------------------
+
+def _nusselt_function():
+    import torch
+
+    class NusseltLoss(torch.autograd.Function):
+        """loss = mean hot-wall Nu_f after nsteps of a lattice created with the
+        porosity and interphase-coefficient fields (phi, Hv).  The forward runs
+        lbm_ltne_adjoint, which produces the loss and both gradients in one
+        call (the reverse sweep needs the forward trajectory anyway); the
+        backward only scales the stored gradients."""
+
+        @staticmethod
+        def forward(ctx, phi, Hv, params, nsteps, ckpt_every):
+            lat = Lattice(params, phi=phi.detach().double().cpu().numpy(),
+                          Hv=Hv.detach().double().cpu().numpy())
+            try:
+                loss, gp, gh = lat.adjoint(int(nsteps), int(ckpt_every))
+            finally:
+                lat.close()
+            ctx.save_for_backward(torch.from_numpy(gp).to(phi.device, phi.dtype),
+                                  torch.from_numpy(gh).to(Hv.device, Hv.dtype))
+            return torch.tensor(loss, dtype=torch.float64, device=phi.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            gp, gh = ctx.saved_tensors
+            s = g.to(gp.dtype)
+            return s * gp, s * gh, None, None, None
+
+    return NusseltLoss
+
+
+_NUSSELT = None
+
+
+def nusselt_loss(params, phi, Hv, nsteps: int, ckpt_every: int = 0):
+    """Differentiable mean hot-wall Nusselt number of the fluid phase after
+    nsteps: a torch scalar whose gradient with respect to the (ny, nx) tensors
+    phi and Hv comes from the hand-written adjoint (lbm_ltne_adjoint)."""
+    global _NUSSELT
+    if _NUSSELT is None:
+        _NUSSELT = _nusselt_function()
+    return _NUSSELT.apply(phi, Hv, params, nsteps, ckpt_every)
+
+
 # --- batched lattices -----------------------------------------------------------
 
 def lbm_ltne_batch_create(params_list, phi_fields=None, Hv_fields=None, hip_stream=None):

@@ -26,10 +26,11 @@
 // back through the force, the velocity solve and the temperature solve.
 //
 // Streaming is a permutation whose adjoint is the push: the adjoint of the
-// pulled population p_i(z) goes to node z - e_i.  Every adjoint population is
-// written exactly once per sweep: by z = y + e_i when that node is interior,
-// as 0 when it is a wall node (wall nodes discard what streams in) or lies
-// outside the lattice (then by y itself).
+// pulled population p_i(z) belongs to population i of node z - e_i.  Each
+// sweep stores mu_i(z) = d<lambda, s*>/dp_i(z) at z itself (aligned stores)
+// and the next sweep gathers lambda_i(y) = mu_i(y + e_i), which is zero where
+// y + e_i is a wall node (wall nodes discard what streams in) or lies
+// outside the lattice: the same shifted-load pattern as the forward pull.
 #pragma once
 
 #include "common.hpp"
@@ -162,9 +163,15 @@ __device__ __forceinline__ void mom_adjoint(const C (&l)[19], MomAdj<C>& m) {
 //        + s3 c1 (eta_e D - (zeta_e - eta_e) theta_f + (1 - eta_e/2) Sr_s - (1 - zeta_e/2) Sr_f),
 // with meq1 = -2 drho + e3, meq2 = drho - e3, S1 = 6 u.rF / phi,
 // S7 = 2 (ux rFx - uy rFy) / phi, S8 = (ux rFy + uy rFx) / phi, c1 = 5 varpi - 4.
-template <typename C>
-__device__ __forceinline__ void adj_interior(const NodeMacros<C>& m, const MomAdj<C>& L, MacroAdj<C>& b,
+template <typename C, typename A>
+__device__ __forceinline__ void adj_interior(const NodeMacros<C>& m, const MomAdj<A>& La, MacroAdj<C>& b,
                                              const StepConsts<C>& k) {
+  MomAdj<C> L;
+  for (int i = 0; i < 9; ++i) L.f[i] = static_cast<C>(La.f[i]);
+  for (int i = 0; i < 5; ++i) {
+    L.a[i] = static_cast<C>(La.a[i]);
+    L.s[i] = static_cast<C>(La.s[i]);
+  }
   const C c1 = C(5) * k.varpi - C(4);
   const C ce = C(1) - C(0.5) * k.s_e, ceps = C(1) - C(0.5) * k.s_eps;
   const C cq = C(1) - C(0.5) * k.s_q, cnu = C(1) - C(0.5) * k.s_nu;
@@ -209,10 +216,16 @@ __device__ __forceinline__ void adj_interior(const NodeMacros<C>& m, const MomAd
 // u_b = 0, T_fb, T_sb = T_fb + D_b and F_b = phi_b (G_b + G(T_fb)).
 // dirichlet: T_fb = T_sb = theta_w (D_b = 0); otherwise T_fb = T_f(z),
 // D_b = D(z).
-template <typename C>
-__device__ __forceinline__ void adj_wall(const NodeMacros<C>& m, const MomAdj<C>& L, C phb, C Hb,
+template <typename C, typename A>
+__device__ __forceinline__ void adj_wall(const NodeMacros<C>& m, const MomAdj<A>& La, C phb, C Hb,
                                          bool dirichlet, C theta_w, MacroAdj<C>& b, C& gpb, C& ghb,
                                          const StepConsts<C>& k) {
+  MomAdj<C> L;
+  for (int i = 0; i < 9; ++i) L.f[i] = static_cast<C>(La.f[i]);
+  for (int i = 0; i < 5; ++i) {
+    L.a[i] = static_cast<C>(La.a[i]);
+    L.s[i] = static_cast<C>(La.s[i]);
+  }
   const C c1 = C(5) * k.varpi - C(4);
   const C cq = C(1) - C(0.5) * k.s_q;
   const C cze = C(1) - C(0.5) * k.z_e, cee = C(1) - C(0.5) * k.e_e;
@@ -349,6 +362,25 @@ __device__ __forceinline__ bool wall_dirichlet(const StepConsts<C>& k, int x, in
 // Index one step outside [0, n) brought back by the periodic wrap.
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// lambda_i at node (x, y): mu_i of the previous sweep at (x, y) + e_i, or 0
+// when that node is a wall node or outside the lattice.
+template <typename Lm, typename C>
+__device__ __forceinline__ void gather_lambda(const Lm* __restrict__ mu, int x, int y, const StepConsts<C>& k,
+                                              Lm (&lam)[19]) {
+  const int nx = k.nx, ny = k.ny;
+  const long long P = k.plane;
+#pragma unroll
+  for (int i = 0; i < kPlanes; ++i) {
+    const int q = i < 9 ? i : (i < 14 ? i - 9 : i - 14);
+    int sx = x + vel_x(q), sy = y + vel_y(q);
+    if (k.px) sx = wrap1(sx, nx);
+    if (k.py) sy = wrap1(sy, ny);
+    const bool inside = sx >= 0 && sx < nx && sy >= 0 && sy < ny;
+    const bool wall = (!k.px && (sx == 0 || sx == nx - 1)) || (!k.py && (sy == 0 || sy == ny - 1));
+    lam[i] = (inside && !wall) ? mu[i * P + (sy * nx + sx)] : Lm(0);
+  }
+}
+
 // The parts of the moment adjoints that the relaxation transpose needs:
 // (1 - s_k) L_k of the non-conserved D2Q9 moments (e, eps, q_x, q_y, p_xx,
 // p_xy) and the non-conserved moments 1..4 of the two thermal lattices.
@@ -357,14 +389,14 @@ struct RelaxAdj {
   C e, eps, qx, qy, pxx, pxy, a[4], s[4];
 };
 
-template <typename C>
-__device__ __forceinline__ void relax_add(RelaxAdj<C>& r, const MomAdj<C>& L, const StepConsts<C>& k) {
-  r.e += (C(1) - k.s_e) * L.f[1];
-  r.eps += (C(1) - k.s_eps) * L.f[2];
-  r.qx += (C(1) - k.s_q) * L.f[4];
-  r.qy += (C(1) - k.s_q) * L.f[6];
-  r.pxx += (C(1) - k.s_nu) * L.f[7];
-  r.pxy += (C(1) - k.s_nu) * L.f[8];
+template <typename A, typename C>
+__device__ __forceinline__ void relax_add(RelaxAdj<A>& r, const MomAdj<A>& L, const StepConsts<C>& k) {
+  r.e += static_cast<A>(C(1) - k.s_e) * L.f[1];
+  r.eps += static_cast<A>(C(1) - k.s_eps) * L.f[2];
+  r.qx += static_cast<A>(C(1) - k.s_q) * L.f[4];
+  r.qy += static_cast<A>(C(1) - k.s_q) * L.f[6];
+  r.pxx += static_cast<A>(C(1) - k.s_nu) * L.f[7];
+  r.pxy += static_cast<A>(C(1) - k.s_nu) * L.f[8];
   for (int i = 0; i < 4; ++i) {
     r.a[i] += L.a[i + 1];
     r.s[i] += L.s[i + 1];
@@ -376,58 +408,123 @@ constexpr int kAdjStep = 0;  // lambda_t -> lambda_{t-1}, gradients of step t
 constexpr int kAdjSeed = 1;  // loss weights on T_f of the last step -> lambda_{N-1}
 constexpr int kAdjInit = 2;  // lambda_0 -> gradients of the initialisation (no push)
 
+// Node enumeration of one adjoint sweep.  Interior nodes next to a wall
+// (x in {1, nx-2} on a walled x axis, y in {1, ny-2} on a walled y axis) also
+// carry the adjoint of the wall nodes rebuilt from them (up to three: two
+// sides and their corner).  They are listed separately (rows first, then the
+// columns without the rows' nodes) and each gets four lanes of one wavefront:
+// lane 0 takes the node's own collision, lanes 1-3 one wall each, in
+// parallel, and the four partial adjoints are summed across the lanes.  The
+// bulk region [bx0, bx0 + bw) x [by0, by0 + bh) takes one lane per node and no
+// wall code, in workgroups of its own placed first in the grid.
+struct AdjGrid {
+  TileMap tm;          // tiles of the bulk region
+  int bx0, by0, bw, bh;
+  int bulk_blocks;     // workgroups of the bulk region (XCD-remapped)
+  int nrow, rowlen, rx0;  // edge rows: y = 1 and (if nrow == 2) y = ny - 2
+  int ncol, collen, cy0;  // edge columns: x = 1 and (if ncol == 2) x = nx - 2
+  int nedge;
+  int edge_blocks;     // workgroups of the edge list, four lanes per node
+};
+
+__device__ __forceinline__ void edge_node(int e, const AdjGrid& g, int nx, int ny, int& x, int& y) {
+  const int nr = g.nrow * g.rowlen;
+  if (e < nr) {
+    const int r = e / g.rowlen;
+    y = (r == 0) ? 1 : ny - 2;
+    x = g.rx0 + (e - r * g.rowlen);
+  } else {
+    e -= nr;
+    const int c = e / g.collen;
+    x = (c == 0) ? 1 : nx - 2;
+    y = g.cy0 + (e - c * g.collen);
+  }
+}
+
+// Sum of v over the four lanes 4j..4j+3 of the wavefront (all lanes take part).
+template <typename T>
+__device__ __forceinline__ T quad_sum(T v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  return v;
+}
+
+template <typename C, typename Lm>
+__device__ __forceinline__ void quad_sum(MacroAdj<C>& b, RelaxAdj<Lm>& r) {
+  for (int j = 0; j < 5; ++j) b.q[j] = quad_sum(b.q[j]);
+  b.rho = quad_sum(b.rho); b.ip = quad_sum(b.ip); b.ux = quad_sum(b.ux); b.uy = quad_sum(b.uy);
+  b.rFx = quad_sum(b.rFx); b.rFy = quad_sum(b.rFy); b.thf = quad_sum(b.thf); b.D = quad_sum(b.D);
+  b.srf = quad_sum(b.srf); b.srs = quad_sum(b.srs); b.dsr = quad_sum(b.dsr);
+  b.e3 = quad_sum(b.e3); b.m7 = quad_sum(b.m7); b.m8 = quad_sum(b.m8); b.jx = quad_sum(b.jx);
+  b.jy = quad_sum(b.jy); b.advx = quad_sum(b.advx); b.advy = quad_sum(b.advy);
+  r.e = quad_sum(r.e); r.eps = quad_sum(r.eps); r.qx = quad_sum(r.qx); r.qy = quad_sum(r.qy);
+  r.pxx = quad_sum(r.pxx); r.pxy = quad_sum(r.pxy);
+  for (int i = 0; i < 4; ++i) {
+    r.a[i] = quad_sum(r.a[i]);
+    r.s[i] = quad_sum(r.s[i]);
+  }
+}
+
 // Lm: storage type of the adjoint populations, C: arithmetic type, R: type
 // of the lattice's fields and recorded sums.
+static_assert(kRows == 1, "the adjoint kernel takes one node (or one part of one) per lane");
+
 template <typename Lm, typename C, typename R, int Mode>
 __global__ __launch_bounds__(kBlock) void adjoint_kernel(
     const Lm* __restrict__ lam_in, Lm* __restrict__ lam_out, const R* __restrict__ rec,
     const R* __restrict__ phi_field, const R* __restrict__ hv_field, double* __restrict__ gphi,
     double* __restrict__ ghv, const R* __restrict__ wseed, const R* __restrict__ init_tf,
-    const R* __restrict__ init_ts, const StepConsts<C> k) {
+    const R* __restrict__ init_ts, const StepConsts<C> k, const AdjGrid g) {
   const int b = blockIdx.x;
-  const int t = (b & (kXcds - 1)) * k.tm.per_xcd + (b >> 3);
-  if (t >= k.tm.ntiles) return;
-  const int tw = 1 << k.tm.tw_shift;
-  const int x = (t % k.tm.ntx) * tw + (static_cast<int>(threadIdx.x) & (tw - 1));
-  const int y0 = (t / k.tm.ntx) * (kBlock >> k.tm.tw_shift) * kRows +
-                 (static_cast<int>(threadIdx.x) >> k.tm.tw_shift);
-  if (x >= k.nx) return;
-  for (int r = 0; r < kRows; ++r) {
-    const int y = y0 + r * (kBlock >> k.tm.tw_shift);
-    if (y >= k.ny) break;
-    const int nx = k.nx, ny = k.ny;
-    const long long P = k.plane;
-    const bool wx = !k.px && (x == 0 || x == nx - 1);
-    const bool wy = !k.py && (y == 0 || y == ny - 1);
-    const int iz = y * nx + x;
-    if (wx || wy) {
-      // Wall node: its pulled populations are never used, and it owns the
-      // adjoint of its own outward populations (no reader).
-      if (Mode == kAdjInit) continue;
-      for (int i = 0; i < kPlanes; ++i) {
-        const int q = i < 9 ? i : (i < 14 ? i - 9 : i - 14);
-        const int ex = vel_x(q), ey = vel_y(q);
-        int sx = x - ex, sy = y - ey;
-        if (k.px) sx = wrap1(sx, nx);
-        if (k.py) sy = wrap1(sy, ny);
-        if (sx >= 0 && sx < nx && sy >= 0 && sy < ny)
-          lam_out[i * P + (sy * nx + sx)] = Lm(0);
-        int tx = x + ex, ty = y + ey;
-        if (k.px) tx = wrap1(tx, nx);
-        if (k.py) ty = wrap1(ty, ny);
-        if (tx < 0 || tx >= nx || ty < 0 || ty >= ny) lam_out[i * P + iz] = Lm(0);
-      }
-      continue;
-    }
-    // ---- interior node z ----
-    // own adjoint populations first, so their loads overlap the arithmetic
-    C lam[19];
-    if (Mode != kAdjSeed)
-      for (int i = 0; i < 19; ++i) lam[i] = static_cast<C>(lam_in[i * P + iz]);
-    NodeMacros<C> m;
+  const int nx = k.nx, ny = k.ny;
+  const long long P = k.plane;
+  // ---- which node, and which part of it, this lane takes ----
+  int x, y, slot = 0;
+  bool valid;
+  if (b < g.bulk_blocks) {
+    const int t = (b & (kXcds - 1)) * g.tm.per_xcd + (b >> 3);
+    if (t >= g.tm.ntiles) return;
+    const int tw = 1 << g.tm.tw_shift;
+    const int xl = (t % g.tm.ntx) * tw + (static_cast<int>(threadIdx.x) & (tw - 1));
+    const int yl = (t / g.tm.ntx) * (kBlock >> g.tm.tw_shift) + (static_cast<int>(threadIdx.x) >> g.tm.tw_shift);
+    if (xl >= g.bw || yl >= g.bh) return;
+    x = g.bx0 + xl;
+    y = g.by0 + yl;
+    valid = true;
+  } else {
+    // four lanes per edge node; every lane of the wavefront stays to the
+    // cross-lane sums
+    const int e4 = (b - g.bulk_blocks) * kBlock + static_cast<int>(threadIdx.x);
+    const int e = e4 >> 2;
+    slot = e4 & 3;
+    valid = e < g.nedge;
+    x = 1;
+    y = 1;
+    if (valid) edge_node(e, g, nx, ny, x, y);
+  }
+  const bool edge = b >= g.bulk_blocks;
+  const int iz = y * nx + x;
+  // the wall this lane takes (slots 1-3), if any
+  const int cx = (!k.px && x == 1) ? 0 : ((!k.px && x == nx - 2) ? nx - 1 : -1);
+  const int cy = (!k.py && y == 1) ? 0 : ((!k.py && y == ny - 2) ? ny - 1 : -1);
+  const bool has_wall = edge && Mode != kAdjSeed &&
+                        ((slot == 1 && cx >= 0) || (slot == 2 && cy >= 0) || (slot == 3 && cx >= 0 && cy >= 0));
+  const bool active = valid && (slot == 0 || has_wall);
+  const int ax = (slot == 2) ? x : cx, ay = (slot == 1) ? y : cy;  // wall node of slots 1-3
+  // own (slot 0) or wall adjoint populations first, so the loads overlap the
+  // arithmetic
+  Lm lam[19];
+  if (Mode != kAdjSeed && active) gather_lambda(lam_in, slot == 0 ? x : ax, slot == 0 ? y : ay, k, lam);
+  NodeMacros<C> m;
+  C D0 = C(0);
+  MacroAdj<C> bar;
+  clear(bar);
+  RelaxAdj<Lm> rx;
+  rx.e = rx.eps = rx.qx = rx.qy = rx.pxx = rx.pxy = Lm(0);
+  for (int i = 0; i < 4; ++i) rx.a[i] = rx.s[i] = Lm(0);
+  if (valid) {
     m.phi = phi_field ? static_cast<C>(phi_field[iz]) : k.phi_u;
     m.H = hv_field ? static_cast<C>(hv_field[iz]) : k.hv_u;
-    C D0 = C(0);
     if (Mode == kAdjInit) {
       // initial pre-collision populations: f = 0 (shifted), g_f = w~ (T_f0 - Sr_f / 2),
       // h = w~ (D0 - (Sr_s - Sr_f) / 2)
@@ -444,114 +541,92 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(
       for (int j = 0; j < 5; ++j) m.q[j] = static_cast<C>(rec[j * k.mplane + iz]);
     }
     node_macros(m, k);
-    MacroAdj<C> bar;
-    clear(bar);
-    RelaxAdj<C> rx;
-    rx.e = rx.eps = rx.qx = rx.qy = rx.pxx = rx.pxy = C(0);
-    for (int i = 0; i < 4; ++i) rx.a[i] = rx.s[i] = C(0);
     if (Mode == kAdjSeed) {
       // the loss weights the reported T_f of the last step
-      bar.thf = static_cast<C>(wseed[iz]);
-    } else {
-      {
-        MomAdj<C> Lz;
-        mom_adjoint(lam, Lz);
-        adj_interior(m, Lz, bar, k);
-        relax_add(rx, Lz, k);
+      if (slot == 0) bar.thf = static_cast<C>(wseed[iz]);
+    } else if (active) {
+      MomAdj<Lm> L;
+      mom_adjoint(lam, L);
+      if (slot == 0) {
+        adj_interior(m, L, bar, k);
+      } else {
+        const int ib = ay * nx + ax;
+        const C phb = phi_field ? static_cast<C>(phi_field[ib]) : k.phi_u;
+        const C hvb = hv_field ? static_cast<C>(hv_field[ib]) : k.hv_u;
+        C thw;
+        const bool dir_w = wall_dirichlet(k, ax, ay, thw);
+        C gpb = C(0), ghb = C(0);
+        adj_wall(m, L, phb, hvb, dir_w, thw, bar, gpb, ghb, k);
+        gphi[ib] += static_cast<double>(gpb);
+        ghv[ib] += static_cast<double>(ghb);
       }
-      // Walls rebuilt from z: at most three (two sides and their corner).
-      const int cx = (!k.px && x == 1) ? 0 : ((!k.px && x == nx - 2) ? nx - 1 : -1);
-      const int cy = (!k.py && y == 1) ? 0 : ((!k.py && y == ny - 2) ? ny - 1 : -1);
-      if (cx >= 0 || cy >= 0) {
-#pragma unroll
-        for (int w = 0; w < 3; ++w) {
-          const bool on = (w == 0) ? (cx >= 0) : ((w == 1) ? (cy >= 0) : (cx >= 0 && cy >= 0));
-          if (!on) continue;
-          const int bx = (w == 1) ? x : cx;
-          const int by = (w == 0) ? y : cy;
-          const int ib = by * nx + bx;
-          for (int i = 0; i < 19; ++i) lam[i] = static_cast<C>(lam_in[i * P + ib]);
-          MomAdj<C> Lw;
-          mom_adjoint(lam, Lw);
-          const C phb = phi_field ? static_cast<C>(phi_field[ib]) : k.phi_u;
-          const C hvb = hv_field ? static_cast<C>(hv_field[ib]) : k.hv_u;
-          C thw;
-          const bool dir_w = wall_dirichlet(k, bx, by, thw);
-          C gpb = C(0), ghb = C(0);
-          adj_wall(m, Lw, phb, hvb, dir_w, thw, bar, gpb, ghb, k);
-          gphi[ib] += static_cast<double>(gpb);
-          ghv[ib] += static_cast<double>(ghb);
-          relax_add(rx, Lw, k);
-        }
-      }
+      relax_add(rx, L, k);
     }
-    C nu[5], gpz, ghz;
-    adj_backprop(m, bar, nu, gpz, ghz, k);
-    // mu = L^T lambda_sum + P^T nu, in population space
-    C mu[19];
-    {
-      // D2Q9: M^T (I - Lambda) lf, rest of the moments vanish (conserved)
-      const C bb = rx.e, c = rx.eps, e = rx.qx, h = rx.qy, p7 = rx.pxx, p8 = rx.pxy;
-      // row i of M^T (I-Lambda) lf = sum_k M[k][i] w_k
-      mu[0] = C(-4) * bb + C(4) * c;
-      mu[1] = -bb - C(2) * c - C(2) * e + p7;
-      mu[2] = -bb - C(2) * c - C(2) * h - p7;
-      mu[3] = -bb - C(2) * c + C(2) * e + p7;
-      mu[4] = -bb - C(2) * c + C(2) * h - p7;
-      mu[5] = C(2) * bb + c + e + h + p8;
-      mu[6] = C(2) * bb + c - e + h - p8;
-      mu[7] = C(2) * bb + c - e - h + p8;
-      mu[8] = C(2) * bb + c + e - h - p8;
-      for (int i = 0; i < 9; ++i) mu[i] += nu[0] + C(vel_x(i)) * nu[1] + C(vel_y(i)) * nu[2];
-      // moments of (L^T lambda): g_f rows take (1 - zeta_k) a_k + (zeta_k - eta_k) s_k,
-      // h rows (1 - eta_k) s_k
-      const C* la = rx.a;  // moments 1..4
-      const C* lh = rx.s;
-      for (int ph = 0; ph < 2; ++ph) {
-        C w1, w2, w3, w4;
-        if (ph == 0) {
-          w1 = (C(1) - k.z_a) * la[0] + (k.z_a - k.e_a) * lh[0];
-          w2 = (C(1) - k.z_a) * la[1] + (k.z_a - k.e_a) * lh[1];
-          w3 = (C(1) - k.z_e) * la[2] + (k.z_e - k.e_e) * lh[2];
-          w4 = (C(1) - k.z_nu) * la[3] + (k.z_nu - k.e_nu) * lh[3];
-        } else {
-          w1 = (C(1) - k.e_a) * lh[0];
-          w2 = (C(1) - k.e_a) * lh[1];
-          w3 = (C(1) - k.e_e) * lh[2];
-          w4 = (C(1) - k.e_nu) * lh[3];
-        }
-        const C ns = nu[3 + ph];
-        C* o = mu + 9 + 5 * ph;
-        o[0] = C(-4) * w3 + ns;
-        o[1] = w1 + w3 + w4 + ns;
-        o[2] = w2 + w3 - w4 + ns;
-        o[3] = -w1 + w3 + w4 + ns;
-        o[4] = -w2 + w3 - w4 + ns;
-      }
-    }
-    double gpd = static_cast<double>(gpz), ghd = static_cast<double>(ghz);
-    if (Mode == kAdjInit) {
-      // the initial populations depend on phi, H through Sr(T_init):
-      // d g_f / dp = -w~ D0 d(d0)/dp, d h / dp = w~ D0 d(d0 + d1)/dp
-      const C w0 = C(1) - k.varpi, w1 = C(0.25) * k.varpi;
-      const C sa = w0 * mu[9] + w1 * (mu[10] + mu[11] + mu[12] + mu[13]);
-      const C sh = w0 * mu[14] + w1 * (mu[15] + mu[16] + mu[17] + mu[18]);
-      const C dd0_dphi = -m.d0 * m.ip, dd1_dphi = m.d1 * m.iq;
-      const C dd0_dh = C(0.5) * k.hvf * m.ip, dd1_dh = C(0.5) * k.hvf * k.inv_sigma * m.iq;
-      gpd += static_cast<double>((-sa * dd0_dphi + sh * (dd0_dphi + dd1_dphi)) * D0);
-      ghd += static_cast<double>((-sa * dd0_dh + sh * (dd0_dh + dd1_dh)) * D0);
-    } else {
-      for (int i = 0; i < kPlanes; ++i) {
-        const int q = i < 9 ? i : (i < 14 ? i - 9 : i - 14);
-        int sx = x - vel_x(q), sy = y - vel_y(q);
-        if (k.px) sx = wrap1(sx, nx);
-        if (k.py) sy = wrap1(sy, ny);
-        lam_out[i * P + (sy * nx + sx)] = static_cast<Lm>(mu[i]);
-      }
-    }
-    gphi[iz] += gpd;
-    ghv[iz] += ghd;
   }
+  if (edge) quad_sum(bar, rx);
+  if (!valid || slot != 0) return;
+  C nu[5], gpz, ghz;
+  adj_backprop(m, bar, nu, gpz, ghz, k);
+  // mu = L^T lambda_sum + P^T nu, in population space
+  Lm mu[19];
+  {
+    // D2Q9: M^T (I - Lambda) lf, rest of the moments vanish (conserved)
+    const Lm bb = rx.e, c = rx.eps, e = rx.qx, h = rx.qy, p7 = rx.pxx, p8 = rx.pxy;
+    const Lm n0 = static_cast<Lm>(nu[0]), n1 = static_cast<Lm>(nu[1]), n2 = static_cast<Lm>(nu[2]);
+    // row i of M^T (I-Lambda) lf = sum_k M[k][i] w_k
+    mu[0] = Lm(-4) * bb + Lm(4) * c;
+    mu[1] = -bb - Lm(2) * c - Lm(2) * e + p7;
+    mu[2] = -bb - Lm(2) * c - Lm(2) * h - p7;
+    mu[3] = -bb - Lm(2) * c + Lm(2) * e + p7;
+    mu[4] = -bb - Lm(2) * c + Lm(2) * h - p7;
+    mu[5] = Lm(2) * bb + c + e + h + p8;
+    mu[6] = Lm(2) * bb + c - e + h - p8;
+    mu[7] = Lm(2) * bb + c - e - h + p8;
+    mu[8] = Lm(2) * bb + c + e - h - p8;
+    for (int i = 0; i < 9; ++i) mu[i] += n0 + Lm(vel_x(i)) * n1 + Lm(vel_y(i)) * n2;
+    // moments of (L^T lambda): g_f rows take (1 - zeta_k) a_k + (zeta_k - eta_k) s_k,
+    // h rows (1 - eta_k) s_k
+    const Lm* la = rx.a;  // moments 1..4
+    const Lm* lh = rx.s;
+    auto cv = [](C v) { return static_cast<Lm>(v); };
+    for (int ph = 0; ph < 2; ++ph) {
+      Lm w1, w2, w3, w4;
+      if (ph == 0) {
+        w1 = cv(C(1) - k.z_a) * la[0] + cv(k.z_a - k.e_a) * lh[0];
+        w2 = cv(C(1) - k.z_a) * la[1] + cv(k.z_a - k.e_a) * lh[1];
+        w3 = cv(C(1) - k.z_e) * la[2] + cv(k.z_e - k.e_e) * lh[2];
+        w4 = cv(C(1) - k.z_nu) * la[3] + cv(k.z_nu - k.e_nu) * lh[3];
+      } else {
+        w1 = cv(C(1) - k.e_a) * lh[0];
+        w2 = cv(C(1) - k.e_a) * lh[1];
+        w3 = cv(C(1) - k.e_e) * lh[2];
+        w4 = cv(C(1) - k.e_nu) * lh[3];
+      }
+      const Lm ns = cv(nu[3 + ph]);
+      Lm* o = mu + 9 + 5 * ph;
+      o[0] = Lm(-4) * w3 + ns;
+      o[1] = w1 + w3 + w4 + ns;
+      o[2] = w2 + w3 - w4 + ns;
+      o[3] = -w1 + w3 + w4 + ns;
+      o[4] = -w2 + w3 - w4 + ns;
+    }
+  }
+  double gpd = static_cast<double>(gpz), ghd = static_cast<double>(ghz);
+  if (Mode == kAdjInit) {
+    // the initial populations depend on phi, H through Sr(T_init):
+    // d g_f / dp = -w~ D0 d(d0)/dp, d h / dp = w~ D0 d(d0 + d1)/dp
+    const C w0 = C(1) - k.varpi, w1 = C(0.25) * k.varpi;
+    const C sa = w0 * C(mu[9]) + w1 * ((C(mu[10]) + C(mu[11])) + (C(mu[12]) + C(mu[13])));
+    const C sh = w0 * C(mu[14]) + w1 * ((C(mu[15]) + C(mu[16])) + (C(mu[17]) + C(mu[18])));
+    const C dd0_dphi = -m.d0 * m.ip, dd1_dphi = m.d1 * m.iq;
+    const C dd0_dh = C(0.5) * k.hvf * m.ip, dd1_dh = C(0.5) * k.hvf * k.inv_sigma * m.iq;
+    gpd += static_cast<double>((-sa * dd0_dphi + sh * (dd0_dphi + dd1_dphi)) * D0);
+    ghd += static_cast<double>((-sa * dd0_dh + sh * (dd0_dh + dd1_dh)) * D0);
+  } else {
+    for (int i = 0; i < kPlanes; ++i) lam_out[i * P + iz] = mu[i];
+  }
+  gphi[iz] += gpd;
+  ghv[iz] += ghd;
 }
 
 }  // namespace ltne

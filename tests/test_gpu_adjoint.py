@@ -186,3 +186,19 @@ def test_512_fp32_adjoint_vs_finite_differences(B):
         say(field, "max|g_FD| %.3e" % scale, "adjoint vs FD %.2e" % err, "FD h vs h/2 %.2e" % cons)
         assert cons <= 1e-4
         assert err <= 1e-4
+
+
+def test_torch_autograd_function(B):
+    """The adjoint behind torch.autograd: loss.backward() fills phi.grad and
+    Hv.grad with the gradients lbm_ltne_adjoint returns, scaled by the
+    upstream gradient."""
+    import torch
+    p, phi, Hv, _ = _small("cavity", I.FP32)
+    ref_loss, ref_p, ref_h = B.Lattice(p, phi=phi, Hv=Hv).adjoint(150, 50)
+    tp = torch.tensor(phi, device="cuda", requires_grad=True)
+    th = torch.tensor(Hv, device="cuda", requires_grad=True)
+    loss = B.nusselt_loss(p, tp, th, 150, 50)
+    assert float(loss) == ref_loss
+    (3.0 * loss).backward()
+    assert np.array_equal(tp.grad.cpu().numpy(), 3.0 * ref_p)
+    assert np.array_equal(th.grad.cpu().numpy(), 3.0 * ref_h)
