@@ -60,7 +60,10 @@ extern "C" {
 /* Storage / arithmetic forms. */
 #define LBM_FP64 0  /* binary64 storage and arithmetic */
 #define LBM_FP32 1  /* binary32 storage and arithmetic, shifted populations */
-#define LBM_FP16S 2 /* binary16 storage of shifted, power-of-two scaled populations; binary32 arithmetic */
+#define LBM_FP16S 2 /* binary16 storage of shifted, power-of-two scaled populations; binary32 arithmetic,
+                       stochastic rounding on store */
+#define LBM_FP32SR 3 /* binary32 storage of shifted populations; binary64 arithmetic, stochastic rounding
+                        on store (rounding errors average out instead of repeating on slowly changing fields) */
 
 /* Thermal wall conditions. */
 #define LBM_WALL_DIRICHLET 0
@@ -78,7 +81,7 @@ typedef struct lbm_ltne_batch *lbm_ltne_batch_t;
  */
 typedef struct lbm_ltne_params {
   int32_t nx, ny;          /* nodes, walls included; >= 4 on a walled axis, >= 3 on a periodic one */
-  int32_t precision;       /* LBM_FP64, LBM_FP32 or LBM_FP16S */
+  int32_t precision;       /* LBM_FP64, LBM_FP32, LBM_FP16S or LBM_FP32SR */
   int32_t periodic_x;      /* 1: periodic along x, 0: walls at x = 0 and x = nx-1 */
   int32_t periodic_y;      /* 1: periodic along y, 0: walls at y = 0 and y = ny-1 */
   int32_t wall_thermal[4]; /* LBM_WALL_* for walls 0..3 (ignored on periodic axes) */
@@ -215,7 +218,7 @@ int lbm_ltne_load(lbm_ltne_t h, const void *host_buf, size_t bytes);
  * (< 1: one segment) and each segment is recomputed once while its
  * per-node sums are recorded.  Work memory of about
  * (nsteps/ckpt_every + 2) state copies + 20 x ckpt_every bytes per node
- * (binary32) is allocated for the call.  FP32 and FP64 forms only
+ * (binary32) is allocated for the call.  FP64, FP32 and FP32SR forms
  * (LBM_EUNSUPPORTED for FP16 storage).  Synchronizes.  On an error the
  * lattice is left at its state on entry (unless the device itself failed).
  */

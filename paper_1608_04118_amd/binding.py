@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbm_ltne
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EDIVERGED, LBM_EUNSUPPORTED, LBM_ENODEV = (
     0, -1, -2, -3, -4, -5, -6)
-LBM_FP64, LBM_FP32, LBM_FP16S = 0, 1, 2
+LBM_FP64, LBM_FP32, LBM_FP16S, LBM_FP32SR = 0, 1, 2, 3
 LBM_WALL_DIRICHLET, LBM_WALL_ADIABATIC = 0, 1
 
 

@@ -43,7 +43,8 @@ struct BatchCtl {
 template <typename S, typename C, int F>
 __device__ __forceinline__ void batch_tile(int t, const CavityDesc<C>* __restrict__ cav,
                                            const StepConsts<C>* __restrict__ ks,
-                                           const int* __restrict__ tile_cav, int parity, bool macros) {
+                                           const int* __restrict__ tile_cav, int parity, bool macros,
+                                           uint32_t step) {
   const int c = tile_cav[t];
   const StepConsts<C>& k = ks[c];
   const CavityDesc<C>& d = cav[c];
@@ -62,9 +63,9 @@ __device__ __forceinline__ void batch_tile(int t, const CavityDesc<C>* __restric
     const int y = y0 + r * th;
     if (y >= k.ny) continue;
     if (macros)
-      node_update<S, C, F | kMacros>(x, y, src, dst, d.phi, d.hv, d.mac, nullptr, nullptr, k);
+      node_update<S, C, F | kMacros>(x, y, src, dst, d.phi, d.hv, d.mac, nullptr, nullptr, k, step);
     else
-      node_update<S, C, F>(x, y, src, dst, d.phi, d.hv, nullptr, nullptr, nullptr, k);
+      node_update<S, C, F>(x, y, src, dst, d.phi, d.hv, nullptr, nullptr, nullptr, k, step);
   }
 }
 
@@ -106,15 +107,15 @@ __device__ __forceinline__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks, un
   return ok != 0;
 }
 
-// nsteps time steps of every lattice.  The tile list is split into 8
-// contiguous ranges, one per XCD (workgroup b runs on XCD b % 8); the grid
-// has a multiple of 8 workgroups.  With persistent = 0 the kernel does one
-// step and needs no barrier.
+// nsteps time steps of every lattice, the first numbered step0.  The tile
+// list is split into 8 contiguous ranges, one per XCD (workgroup b runs on
+// XCD b % 8); the grid has a multiple of 8 workgroups.  With persistent = 0
+// the kernel does one step and needs no barrier.
 template <typename S, typename C, int F>
 __global__ __launch_bounds__(kBlock) void batch_kernel(
     const CavityDesc<C>* __restrict__ cav, const StepConsts<C>* __restrict__ ks,
     const int* __restrict__ tile_cav, int ntiles, int nsteps, int parity0, int macros_last,
-    BatchCtl* ctl, unsigned spin_limit) {
+    BatchCtl* ctl, unsigned spin_limit, uint32_t step0) {
   const int xcd = blockIdx.x & (kXcds - 1);
   const int slot = blockIdx.x >> 3;
   const int slots = gridDim.x >> 3;
@@ -125,7 +126,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(
   for (int s = 0; s < nsteps; ++s) {
     const int parity = (parity0 + s) & 1;
     const bool macros = macros_last && (s == nsteps - 1);
-    for (int t = t0 + slot; t < t1; t += slots) batch_tile<S, C, F>(t, cav, ks, tile_cav, parity, macros);
+    for (int t = t0 + slot; t < t1; t += slots)
+      batch_tile<S, C, F>(t, cav, ks, tile_cav, parity, macros, step0 + static_cast<uint32_t>(s));
     if (s + 1 < nsteps && !grid_barrier(ctl, gridDim.x, gen, spin_limit)) return;
   }
 }
@@ -196,7 +198,7 @@ int upload_tables_t(lbm_ltne_batch* b) {
 }
 
 int upload_tables(lbm_ltne_batch* b) {
-  return b->precision == LBM_FP64 ? upload_tables_t<double>(b) : upload_tables_t<float>(b);
+  return compute_bytes(b->precision) == 8 ? upload_tables_t<double>(b) : upload_tables_t<float>(b);
 }
 
 template <typename S, typename C, int F>
@@ -217,6 +219,7 @@ const void* pick_fn(int fields) {
 const void* batch_function(const lbm_ltne_batch* b) {
   if (b->precision == LBM_FP64) return pick_fn<double, double>(b->fields);
   if (b->precision == LBM_FP32) return pick_fn<float, float>(b->fields);
+  if (b->precision == LBM_FP32SR) return pick_fn<float, double>(b->fields);
   return pick_fn<_Float16, float>(b->fields);
 }
 
@@ -246,7 +249,8 @@ int launch_batch(lbm_ltne_batch* b, int nsteps, int macros_last) {
   if (b->persistent) {
     HIP_TRY(hipMemsetAsync(ctl, 0, sizeof(BatchCtl), b->stream));
     int parity = b->parity;
-    void* args[] = {&cav, &ks, &tiles, &ntiles, &nsteps, &parity, &macros_last, &ctl, &spin};
+    uint32_t step0 = static_cast<uint32_t>(b->steps + 1);
+    void* args[] = {&cav, &ks, &tiles, &ntiles, &nsteps, &parity, &macros_last, &ctl, &spin, &step0};
     HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(b->grid), dim3(kBlock), args, 0, b->stream));
   } else {
     const int per = (ntiles + kXcds - 1) / kXcds;
@@ -255,7 +259,8 @@ int launch_batch(lbm_ltne_batch* b, int nsteps, int macros_last) {
       int one = 1;
       int parity = (b->parity + s) & 1;
       int mac = (macros_last && s == nsteps - 1) ? 1 : 0;
-      void* args[] = {&cav, &ks, &tiles, &ntiles, &one, &parity, &mac, &ctl, &spin};
+      uint32_t step0 = static_cast<uint32_t>(b->steps + 1 + s);
+      void* args[] = {&cav, &ks, &tiles, &ntiles, &one, &parity, &mac, &ctl, &spin, &step0};
       HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, b->stream));
     }
   }
@@ -285,19 +290,19 @@ hipError_t init_one(const lbm_ltne_batch* b, int i) {
   switch (fl) {
     case 0:
       hipLaunchKernelGGL((step_kernel<S, C, kMacros | kInit>), grid, block, 0, b->stream, nullptr,
-                         dst, phi, hv, mac, nullptr, nullptr, k);
+                         dst, phi, hv, mac, nullptr, nullptr, k, 0u);
       break;
     case kPhiField:
       hipLaunchKernelGGL((step_kernel<S, C, kPhiField | kMacros | kInit>), grid, block, 0, b->stream,
-                         nullptr, dst, phi, hv, mac, nullptr, nullptr, k);
+                         nullptr, dst, phi, hv, mac, nullptr, nullptr, k, 0u);
       break;
     case kHvField:
       hipLaunchKernelGGL((step_kernel<S, C, kHvField | kMacros | kInit>), grid, block, 0, b->stream,
-                         nullptr, dst, phi, hv, mac, nullptr, nullptr, k);
+                         nullptr, dst, phi, hv, mac, nullptr, nullptr, k, 0u);
       break;
     default:
       hipLaunchKernelGGL((step_kernel<S, C, kPhiField | kHvField | kMacros | kInit>), grid, block, 0,
-                         b->stream, nullptr, dst, phi, hv, mac, nullptr, nullptr, k);
+                         b->stream, nullptr, dst, phi, hv, mac, nullptr, nullptr, k, 0u);
   }
   return hipGetLastError();
 }
@@ -305,11 +310,12 @@ hipError_t init_one(const lbm_ltne_batch* b, int i) {
 hipError_t init_lattice(const lbm_ltne_batch* b, int i) {
   if (b->precision == LBM_FP64) return init_one<double, double>(b, i);
   if (b->precision == LBM_FP32) return init_one<float, float>(b, i);
+  if (b->precision == LBM_FP32SR) return init_one<float, double>(b, i);
   return init_one<_Float16, float>(b, i);
 }
 
 int upload_batch_field(const lbm_ltne_batch* b, const double* src, size_t off, long long n) {
-  if (b->precision == LBM_FP64) {
+  if (compute_bytes(b->precision) == 8) {
     HIP_TRY(hipMemcpyAsync(b->base + off, src, n * sizeof(double), hipMemcpyHostToDevice, b->stream));
   } else {
     std::vector<float> tmp(n);
@@ -391,8 +397,9 @@ int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params* ps, const double* co
     for (int sh = 6; sh <= 8; ++sh) most = std::max(most, make_tiles(ps[i].nx, ps[i].ny, precision, sh).ntiles);
     b->max_tiles += most;
   }
-  b->consts_bytes = (precision == LBM_FP64 ? sizeof(StepConsts<double>) : sizeof(StepConsts<float>));
-  b->desc_bytes = (precision == LBM_FP64 ? sizeof(CavityDesc<double>) : sizeof(CavityDesc<float>));
+  const bool cdouble = compute_bytes(precision) == 8;
+  b->consts_bytes = (cdouble ? sizeof(StepConsts<double>) : sizeof(StepConsts<float>));
+  b->desc_bytes = (cdouble ? sizeof(CavityDesc<double>) : sizeof(CavityDesc<float>));
   b->off_consts = o; o += align_up(n * b->consts_bytes, kAlign);
   b->off_cav = o; o += align_up(n * b->desc_bytes, kAlign);
   b->off_tiles = o; o += align_up(static_cast<size_t>(b->max_tiles) * sizeof(int), kAlign);
@@ -614,7 +621,7 @@ int lbm_ltne_batch_nusselt(lbm_ltne_batch_t b, int32_t i, double* Nu_f, double* 
   const double scale = b->d[i].L / b->d[i].dT;
   double* res = reinterpret_cast<double*>(b->base + b->off_result);
   const long long n = b->n_of(i);
-  if (b->precision == LBM_FP64)
+  if (compute_bytes(b->precision) == 8)
     hipLaunchKernelGGL((nusselt_kernel<double>), dim3(1), dim3(kBlock), 0, b->stream,
                        reinterpret_cast<const double*>(b->base + b->off_mac[i]), p.nx, p.ny, n, w,
                        periodic_t, scale, res);

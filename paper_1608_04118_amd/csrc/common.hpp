@@ -50,6 +50,20 @@ __host__ __device__ constexpr int vel_y(int i) {
   return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
 }
 
+// 32-bit integer mixer (xor-shift / multiply rounds of the kind used as the
+// finalizer of MurmurHash3; constants from Wellons' low-bias search): every
+// input bit affects every output bit.  Source of the stochastic-rounding bits,
+// counter-based so a result depends only on (node, step), never on the
+// launch shape or the order of execution.
+__host__ __device__ constexpr uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
 // Flags of the fused step kernel.
 constexpr int kPhiField = 1;  // per-node porosity
 constexpr int kHvField = 2;   // per-node interphase coefficient

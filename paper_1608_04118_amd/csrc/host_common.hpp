@@ -26,9 +26,9 @@ constexpr uint32_t kStateMagic = 0x484e544cu;  // "LTNH": f, g_f and h = g_s - g
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 inline size_t storage_bytes(int precision) {
-  return precision == LBM_FP64 ? 8 : (precision == LBM_FP32 ? 4 : 2);
+  return precision == LBM_FP64 ? 8 : ((precision == LBM_FP32 || precision == LBM_FP32SR) ? 4 : 2);
 }
-inline size_t compute_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
+inline size_t compute_bytes(int precision) { return (precision == LBM_FP64 || precision == LBM_FP32SR) ? 8 : 4; }
 
 // Elements between population planes: the plane rounded up to 1024 elements
 // plus a pad (kPlanePad; 8192 binary16 elements = 16 KiB for large FP16

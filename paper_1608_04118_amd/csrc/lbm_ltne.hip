@@ -50,14 +50,14 @@ void fill_consts(const lbm_ltne* h, StepConsts<C>* k) {
 }
 
 template <typename S, typename C, int F>
-hipError_t launch_one(const lbm_ltne* h, const StepConsts<C>& k, const void* src, void* dst,
+hipError_t launch_one(const lbm_ltne* h, const StepConsts<C>& k, uint32_t step, const void* src, void* dst,
                       void* mac, const void* init_tf, const void* init_ts, void* rec = nullptr) {
   const dim3 grid(grid_blocks(k.tm)), block(kBlock);
   hipLaunchKernelGGL((step_kernel<S, C, F>), grid, block, 0, h->stream,
                      static_cast<const S*>(src), static_cast<S*>(dst),
                      static_cast<const C*>(h->phi()), static_cast<const C*>(h->hv()),
                      static_cast<C*>(mac), static_cast<const C*>(init_tf),
-                     static_cast<const C*>(init_ts), k, static_cast<C*>(rec));
+                     static_cast<const C*>(init_ts), k, step, static_cast<C*>(rec));
   return hipGetLastError();
 }
 
@@ -65,7 +65,7 @@ hipError_t launch_one(const lbm_ltne* h, const StepConsts<C>& k, const void* src
 // 2 initialisation (writes macros), 3 step recording q at interior nodes,
 // 4 recording step that also writes macros (modes 3, 4: FP32 and FP64 only).
 template <typename S, typename C>
-hipError_t launch_step_t(const lbm_ltne* h, const StepConsts<C>& k, int mode, const void* src,
+hipError_t launch_step_t(const lbm_ltne* h, const StepConsts<C>& k, int mode, uint32_t step, const void* src,
                          void* dst, void* mac, const void* init_tf, const void* init_ts,
                          void* rec) {
   const int fl = (h->has_phi ? kPhiField : 0) | (h->has_hv ? kHvField : 0);
@@ -73,20 +73,20 @@ hipError_t launch_step_t(const lbm_ltne* h, const StepConsts<C>& k, int mode, co
     if (mode == 3 || mode == 4) {
       switch (fl) {
         case 0:
-          return mode == 3 ? launch_one<S, C, kRecord>(h, k, src, dst, mac, init_tf, init_ts, rec)
-                           : launch_one<S, C, kRecord | kMacros>(h, k, src, dst, mac, init_tf, init_ts, rec);
+          return mode == 3 ? launch_one<S, C, kRecord>(h, k, step, src, dst, mac, init_tf, init_ts, rec)
+                           : launch_one<S, C, kRecord | kMacros>(h, k, step, src, dst, mac, init_tf, init_ts, rec);
         case kPhiField:
-          return mode == 3 ? launch_one<S, C, kPhiField | kRecord>(h, k, src, dst, mac, init_tf, init_ts, rec)
-                           : launch_one<S, C, kPhiField | kRecord | kMacros>(h, k, src, dst, mac, init_tf,
+          return mode == 3 ? launch_one<S, C, kPhiField | kRecord>(h, k, step, src, dst, mac, init_tf, init_ts, rec)
+                           : launch_one<S, C, kPhiField | kRecord | kMacros>(h, k, step, src, dst, mac, init_tf,
                                                                             init_ts, rec);
         case kHvField:
-          return mode == 3 ? launch_one<S, C, kHvField | kRecord>(h, k, src, dst, mac, init_tf, init_ts, rec)
-                           : launch_one<S, C, kHvField | kRecord | kMacros>(h, k, src, dst, mac, init_tf,
+          return mode == 3 ? launch_one<S, C, kHvField | kRecord>(h, k, step, src, dst, mac, init_tf, init_ts, rec)
+                           : launch_one<S, C, kHvField | kRecord | kMacros>(h, k, step, src, dst, mac, init_tf,
                                                                            init_ts, rec);
         default:
           return mode == 3
-                     ? launch_one<S, C, kPhiField | kHvField | kRecord>(h, k, src, dst, mac, init_tf, init_ts, rec)
-                     : launch_one<S, C, kPhiField | kHvField | kRecord | kMacros>(h, k, src, dst, mac, init_tf,
+                     ? launch_one<S, C, kPhiField | kHvField | kRecord>(h, k, step, src, dst, mac, init_tf, init_ts, rec)
+                     : launch_one<S, C, kPhiField | kHvField | kRecord | kMacros>(h, k, step, src, dst, mac, init_tf,
                                                                                  init_ts, rec);
       }
     }
@@ -96,9 +96,9 @@ hipError_t launch_step_t(const lbm_ltne* h, const StepConsts<C>& k, int mode, co
   }
 #define LTNE_CASE(FL)                                                                               \
   case FL:                                                                                          \
-    if (mode == 0) return launch_one<S, C, FL>(h, k, src, dst, mac, init_tf, init_ts);               \
-    if (mode == 1) return launch_one<S, C, FL | kMacros>(h, k, src, dst, mac, init_tf, init_ts);     \
-    return launch_one<S, C, FL | kMacros | kInit>(h, k, src, dst, mac, init_tf, init_ts);
+    if (mode == 0) return launch_one<S, C, FL>(h, k, step, src, dst, mac, init_tf, init_ts);               \
+    if (mode == 1) return launch_one<S, C, FL | kMacros>(h, k, step, src, dst, mac, init_tf, init_ts);     \
+    return launch_one<S, C, FL | kMacros | kInit>(h, k, step, src, dst, mac, init_tf, init_ts);
   switch (fl) {
     LTNE_CASE(0)
     LTNE_CASE(kPhiField)
@@ -109,22 +109,27 @@ hipError_t launch_step_t(const lbm_ltne* h, const StepConsts<C>& k, int mode, co
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_step(const lbm_ltne* h, int mode, const void* src, void* dst, void* mac,
+// step: the number of the time step being computed (0 for the
+// initialisation), the counter of the stochastic rounding.
+hipError_t launch_step(const lbm_ltne* h, int mode, int64_t step, const void* src, void* dst, void* mac,
                        const void* init_tf, const void* init_ts, void* rec = nullptr) {
+  const uint32_t st = static_cast<uint32_t>(step);
   switch (h->p.precision) {
     case LBM_FP64:
-      return launch_step_t<double, double>(h, h->kd, mode, src, dst, mac, init_tf, init_ts, rec);
+      return launch_step_t<double, double>(h, h->kd, mode, st, src, dst, mac, init_tf, init_ts, rec);
     case LBM_FP32:
-      return launch_step_t<float, float>(h, h->kf, mode, src, dst, mac, init_tf, init_ts, rec);
+      return launch_step_t<float, float>(h, h->kf, mode, st, src, dst, mac, init_tf, init_ts, rec);
+    case LBM_FP32SR:
+      return launch_step_t<float, double>(h, h->kd, mode, st, src, dst, mac, init_tf, init_ts, rec);
     default:
-      return launch_step_t<_Float16, float>(h, h->kf, mode, src, dst, mac, init_tf, init_ts, rec);
+      return launch_step_t<_Float16, float>(h, h->kf, mode, st, src, dst, mac, init_tf, init_ts, rec);
   }
 }
 
 // Copies a host double field to device memory in the compute type.
 int upload_field(const lbm_ltne* h, const double* src, void* dst) {
   const long long n = h->n();
-  if (h->p.precision == LBM_FP64) {
+  if (compute_bytes(h->p.precision) == 8) {
     HIP_TRY(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
   } else {
     std::vector<float> tmp(n);
@@ -249,7 +254,7 @@ int lbm_ltne_create(const lbm_ltne_params* p, const double* phi_field, const dou
     }
   }
   if (rc == LBM_OK) {
-    hipError_t e = launch_step(h, 2, nullptr, h->pop(0), h->mac(0), tf_dev, ts_dev);
+    hipError_t e = launch_step(h, 2, 0, nullptr, h->pop(0), h->mac(0), tf_dev, ts_dev);
     if (e != hipSuccess) rc = set_error(LBM_EHIP, "initialisation launch: %s", hipGetErrorString(e));
   }
   if (rc == LBM_OK) {
@@ -276,7 +281,7 @@ int lbm_ltne_step(lbm_ltne_t h, int64_t nsteps) {
   if (nsteps == 0) return LBM_OK;
   for (int64_t s = 0; s < nsteps; ++s) {
     const bool last = (s == nsteps - 1);
-    hipError_t e = launch_step(h, last ? 1 : 0, h->pop(h->cur), h->pop(1 - h->cur),
+    hipError_t e = launch_step(h, last ? 1 : 0, h->steps + 1, h->pop(h->cur), h->pop(1 - h->cur),
                                last ? h->mac(1 - h->mcur) : nullptr, nullptr, nullptr);
     if (e != hipSuccess) return set_error(LBM_EHIP, "step launch: %s", hipGetErrorString(e));
     h->cur = 1 - h->cur;
@@ -316,7 +321,7 @@ int lbm_ltne_nusselt(lbm_ltne_t h, double* Nu_f, double* Nu_s) {
   if (w < 0) return set_error(LBM_EINVAL, "no wall selected for the Nusselt number");
   const int periodic_t = (w < 2) ? h->p.periodic_y : h->p.periodic_x;
   const double scale = h->d.L / h->d.dT;
-  if (h->p.precision == LBM_FP64) {
+  if (compute_bytes(h->p.precision) == 8) {
     hipLaunchKernelGGL((nusselt_kernel<double>), dim3(1), dim3(kBlock), 0, h->stream,
                        static_cast<const double*>(h->mac(h->mcur)), h->p.nx, h->p.ny, h->n(), w,
                        periodic_t, scale, h->result());
@@ -338,7 +343,7 @@ int lbm_ltne_diagnostics(lbm_ltne_t h, double* mass, double* energy, double* res
   if (!h) return set_error(LBM_EINVAL, "handle is NULL");
   const long long n = h->n();
   const int blocks = static_cast<int>(std::min<long long>(kSumBlocks, (n + kBlock - 1) / kBlock));
-  if (h->p.precision == LBM_FP64) {
+  if (compute_bytes(h->p.precision) == 8) {
     hipLaunchKernelGGL((sums_kernel<double>), dim3(blocks), dim3(kBlock), 0, h->stream,
                        static_cast<const double*>(h->mac(h->mcur)),
                        static_cast<const double*>(h->mac(1 - h->mcur)),
@@ -537,6 +542,7 @@ int adjoint_t(lbm_ltne* h, int64_t nsteps, int64_t K, double* loss, double* dphi
   const int w = hot_wall(&h->p);
   if (w < 0) return set_error(LBM_EINVAL, "no wall selected for the Nusselt number");
   const bool include_init = (h->steps == 0);
+  const int64_t t0 = h->steps;
   const int64_t nseg = (nsteps + K - 1) / K;
   const size_t popb = h->lay.pop_bytes;
   const size_t recb = align_up(static_cast<size_t>(K) * 5 * n * sizeof(R), kAlign);
@@ -591,7 +597,7 @@ int adjoint_t(lbm_ltne* h, int64_t nsteps, int64_t K, double* loss, double* dphi
     if (e != hipSuccess) return sg == 0 ? hip_fail(e, "checkpoint") : bail(hip_fail(e, "checkpoint"));
     const int64_t steps_in = std::min<int64_t>(K, nsteps - sg * K);
     for (int64_t j = 0; j < steps_in; ++j) {
-      e = launch_step(h, 0, h->pop(h->cur), h->pop(1 - h->cur), nullptr, nullptr, nullptr);
+      e = launch_step(h, 0, t0 + sg * K + j + 1, h->pop(h->cur), h->pop(1 - h->cur), nullptr, nullptr, nullptr);
       if (e != hipSuccess) return bail(hip_fail(e, "forward launch"));
       h->cur = 1 - h->cur;
     }
@@ -618,8 +624,8 @@ int adjoint_t(lbm_ltne* h, int64_t nsteps, int64_t K, double* loss, double* dphi
     int wc = 0;
     for (int64_t j = 1; j <= steps_in; ++j) {
       const bool last = (sg == nseg - 1 && j == steps_in);
-      e = launch_step(h, last ? 4 : 3, work[wc], work[1 - wc], last ? h->mac(1 - h->mcur) : nullptr,
-                      nullptr, nullptr, rec + (j - 1) * 5 * n);
+      e = launch_step(h, last ? 4 : 3, t0 + sg * K + j, work[wc], work[1 - wc],
+                      last ? h->mac(1 - h->mcur) : nullptr, nullptr, nullptr, rec + (j - 1) * 5 * n);
       if (e != hipSuccess) return bail(hip_fail(e, "recompute launch"));
       wc = 1 - wc;
     }
@@ -679,9 +685,11 @@ extern "C" int lbm_ltne_adjoint(lbm_ltne_t h, int64_t nsteps, int64_t ckpt_every
   if (ckpt_every < 1) ckpt_every = nsteps;
   if (ckpt_every > nsteps) ckpt_every = nsteps;
   if (h->p.precision == LBM_FP16S)
-    return set_error(LBM_EUNSUPPORTED, "the adjoint is built for the FP32 and FP64 forms");
+    return set_error(LBM_EUNSUPPORTED, "the adjoint is built for the FP64, FP32 and FP32SR forms");
   if (h->p.precision == LBM_FP64)
     return adjoint_t<double, double, double>(h, nsteps, ckpt_every, loss, dL_dphi, dL_dHv);
+  if (h->p.precision == LBM_FP32SR)
+    return adjoint_t<double, LTNE_ADJ32_LAM, LTNE_ADJ32_MATH>(h, nsteps, ckpt_every, loss, dL_dphi, dL_dHv);
   return adjoint_t<float, LTNE_ADJ32_LAM, LTNE_ADJ32_MATH>(h, nsteps, ckpt_every, loss, dL_dphi, dL_dHv);
 }
 

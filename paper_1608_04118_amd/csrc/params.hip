@@ -83,8 +83,8 @@ int derive(const lbm_ltne_params* p, double tmin, double tmax, lbm_ltne_derived*
   std::memset(d, 0, sizeof(*d));
   if (!p) return set_error(LBM_EINVAL, "params is NULL");
   if (!finite_all(p)) return set_error(LBM_EINVAL, "a parameter is not finite");
-  if (p->precision < LBM_FP64 || p->precision > LBM_FP16S)
-    return set_error(LBM_EINVAL, "precision %d is not LBM_FP64, LBM_FP32 or LBM_FP16S", p->precision);
+  if (p->precision < LBM_FP64 || p->precision > LBM_FP32SR)
+    return set_error(LBM_EINVAL, "precision %d is not LBM_FP64, LBM_FP32, LBM_FP16S or LBM_FP32SR", p->precision);
   if ((p->periodic_x != 0 && p->periodic_x != 1) || (p->periodic_y != 0 && p->periodic_y != 1))
     return set_error(LBM_EINVAL, "periodic_x / periodic_y must be 0 or 1");
   const int minx = p->periodic_x ? 3 : 4, miny = p->periodic_y ? 3 : 4;

@@ -61,12 +61,33 @@ __device__ __forceinline__ void store_raw(S* __restrict__ p, S v) {
   }
 }
 
+// Storage forms narrower than the arithmetic round stochastically: r16
+// (16 random bits) is added below the kept significand bits, which are then
+// truncated, so a value is rounded up with probability equal to its distance
+// from the lower neighbour in units of the last place.  The expected stored
+// value is the exact one: rounding errors no longer repeat themselves step
+// after step on a slowly changing field (where round-to-nearest would add
+// the same error at every step), they average out.
 template <typename S, typename C>
-__device__ __forceinline__ void store_pop(S* __restrict__ p, C v, C scale) {
+constexpr bool kStochastic = !std::is_same<S, C>::value;
+
+template <typename S, typename C>
+__device__ __forceinline__ void store_pop(S* __restrict__ p, C v, C scale, uint32_t r16) {
   if constexpr (std::is_same<S, _Float16>::value) {
-    store_raw(p, static_cast<_Float16>(static_cast<float>(v * scale)));
+    // binary32 -> binary16: 13 discarded significand bits
+    uint32_t u = __float_as_uint(static_cast<float>(v * scale)) + (r16 >> 3);
+    u &= ~0x1fffu;
+    store_raw(p, static_cast<_Float16>(__uint_as_float(u)));  // exact for normal binary16 values
+  } else if constexpr (std::is_same<S, float>::value && std::is_same<C, double>::value) {
+    // binary64 -> binary32: 29 discarded significand bits
+    (void)scale;
+    unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v)) +
+                           (static_cast<unsigned long long>(r16) << 13);
+    u &= ~0x1fffffffull;
+    store_raw(p, static_cast<float>(__longlong_as_double(static_cast<long long>(u))));  // exact
   } else {
     (void)scale;
+    (void)r16;
     store_raw(p, static_cast<S>(v));
   }
 }
@@ -102,13 +123,15 @@ __device__ __forceinline__ C dev_sqrt(C v) {
   }
 }
 
-// One node update: pull, macros, walls, collisions, store.
+// One node update: pull, macros, walls, collisions, store.  step numbers
+// the time step being computed (0: initialisation); with a narrow storage
+// form it seeds the stochastic rounding of the stores.
 template <typename S, typename C, int F>
 __device__ __forceinline__ void node_update(
     const int x, const int y, const S* __restrict__ src, S* __restrict__ dst,
     const C* __restrict__ phi_field, const C* __restrict__ hv_field, C* __restrict__ mac,
     const C* __restrict__ init_tf, const C* __restrict__ init_ts, const StepConsts<C>& k,
-    C* __restrict__ rec = nullptr) {
+    const uint32_t step, C* __restrict__ rec = nullptr) {
   const int nx = k.nx, ny = k.ny;
 
   // Wall classification and the node whose post-streaming populations this
@@ -336,6 +359,16 @@ __device__ __forceinline__ void node_update(
 
   const long long P = k.plane;
   const int io = y * nx + x;
+  // 19 x 16 random bits for the stores (unused by the same-type forms)
+  uint32_t rb[10];
+  if constexpr (kStochastic<S, C>) {
+    const uint32_t base = mix32(static_cast<uint32_t>(io) ^ mix32(step * 0x9e3779b9u + 0x632be5abu));
+#pragma unroll
+    for (int j = 0; j < 10; ++j) rb[j] = mix32(base + static_cast<uint32_t>(j) * 0x85ebca77u);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 10; ++j) rb[j] = 0u;
+  }
 
   // ---- D2Q9 collision in moment space (Eq. 10) ----
   {
@@ -393,15 +426,15 @@ __device__ __forceinline__ void node_update(
     const C o4 = o2 + ((o5 + o6) - (o7 + o8)) - ms5;
     const C o0 = ms0 - (((o1 + o2) + (o3 + o4)) + ((o5 + o6) + (o7 + o8)));
     const C sf = k.sf;
-    store_pop(at(dst + 0 * P, io), o0, sf);
-    store_pop(at(dst + 1 * P, io), o1, sf);
-    store_pop(at(dst + 2 * P, io), o2, sf);
-    store_pop(at(dst + 3 * P, io), o3, sf);
-    store_pop(at(dst + 4 * P, io), o4, sf);
-    store_pop(at(dst + 5 * P, io), o5, sf);
-    store_pop(at(dst + 6 * P, io), o6, sf);
-    store_pop(at(dst + 7 * P, io), o7, sf);
-    store_pop(at(dst + 8 * P, io), o8, sf);
+    store_pop(at(dst + 0 * P, io), o0, sf, (rb[0] & 0xffffu));
+    store_pop(at(dst + 1 * P, io), o1, sf, (rb[0] >> 16));
+    store_pop(at(dst + 2 * P, io), o2, sf, (rb[1] & 0xffffu));
+    store_pop(at(dst + 3 * P, io), o3, sf, (rb[1] >> 16));
+    store_pop(at(dst + 4 * P, io), o4, sf, (rb[2] & 0xffffu));
+    store_pop(at(dst + 5 * P, io), o5, sf, (rb[2] >> 16));
+    store_pop(at(dst + 6 * P, io), o6, sf, (rb[3] & 0xffffu));
+    store_pop(at(dst + 7 * P, io), o7, sf, (rb[3] >> 16));
+    store_pop(at(dst + 8 * P, io), o8, sf, (rb[4] & 0xffffu));
   }
 
   // ---- D2Q5 collisions (Eqs. 32, 33) ----
@@ -427,11 +460,11 @@ __device__ __forceinline__ void node_update(
       const C r1 = o0 + h1 + o3 + o4, r2 = o0 + h2 + o3 - o4;
       const C r3 = o0 - h1 + o3 + o4, r4 = o0 - h2 + o3 - o4;
       // rest population from the conserved zeroth moment (see the flow part)
-      store_pop(at(dst + 9 * P, io), nf0 - ((r1 + r2) + (r3 + r4)), sg);
-      store_pop(at(dst + 10 * P, io), r1, sg);
-      store_pop(at(dst + 11 * P, io), r2, sg);
-      store_pop(at(dst + 12 * P, io), r3, sg);
-      store_pop(at(dst + 13 * P, io), r4, sg);
+      store_pop(at(dst + 9 * P, io), nf0 - ((r1 + r2) + (r3 + r4)), sg, (rb[4] >> 16));
+      store_pop(at(dst + 10 * P, io), r1, sg, (rb[5] & 0xffffu));
+      store_pop(at(dst + 11 * P, io), r2, sg, (rb[5] >> 16));
+      store_pop(at(dst + 12 * P, io), r3, sg, (rb[6] & 0xffffu));
+      store_pop(at(dst + 13 * P, io), r4, sg, (rb[6] >> 16));
     }
     // solid phase (Eq. 33, equilibria of Eq. 38), carried as the difference
     // g_s - g_f: in moments, n_h* = n_s* - n_f* with n_s = n_f + n_h,
@@ -458,11 +491,11 @@ __device__ __forceinline__ void node_update(
       const C h1 = ns1 * C(0.5), h2 = ns2 * C(0.5);
       const C r1 = o0 + h1 + o3 + o4, r2 = o0 + h2 + o3 - o4;
       const C r3 = o0 - h1 + o3 + o4, r4 = o0 - h2 + o3 - o4;
-      store_pop(at(dst + 14 * P, io), nh0 - ((r1 + r2) + (r3 + r4)), sg);
-      store_pop(at(dst + 15 * P, io), r1, sg);
-      store_pop(at(dst + 16 * P, io), r2, sg);
-      store_pop(at(dst + 17 * P, io), r3, sg);
-      store_pop(at(dst + 18 * P, io), r4, sg);
+      store_pop(at(dst + 14 * P, io), nh0 - ((r1 + r2) + (r3 + r4)), sg, (rb[7] & 0xffffu));
+      store_pop(at(dst + 15 * P, io), r1, sg, (rb[7] >> 16));
+      store_pop(at(dst + 16 * P, io), r2, sg, (rb[8] & 0xffffu));
+      store_pop(at(dst + 17 * P, io), r3, sg, (rb[8] >> 16));
+      store_pop(at(dst + 18 * P, io), r4, sg, (rb[9] & 0xffffu));
     }
   }
 }
@@ -473,7 +506,7 @@ template <typename S, typename C, int F>
 __global__ __launch_bounds__(kBlock) void step_kernel(
     const S* __restrict__ src, S* __restrict__ dst, const C* __restrict__ phi_field,
     const C* __restrict__ hv_field, C* __restrict__ mac, const C* __restrict__ init_tf,
-    const C* __restrict__ init_ts, const StepConsts<C> k, C* __restrict__ rec = nullptr) {
+    const C* __restrict__ init_ts, const StepConsts<C> k, const uint32_t step, C* __restrict__ rec = nullptr) {
   const int b = blockIdx.x;
   const int t = kXcdRemap ? (b & (kXcds - 1)) * k.tm.per_xcd + (b >> 3) : b;
   if (t >= k.tm.ntiles) return;
@@ -487,7 +520,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(
 #pragma unroll
   for (int r = 0; r < kRows; ++r) {
     const int y = y0 + r * th;
-    if (y < k.ny) node_update<S, C, F>(x, y, src, dst, phi_field, hv_field, mac, init_tf, init_ts, k, rec);
+    if (y < k.ny) node_update<S, C, F>(x, y, src, dst, phi_field, hv_field, mac, init_tf, init_ts, k, step, rec);
   }
 }
 

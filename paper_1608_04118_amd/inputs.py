@@ -26,7 +26,7 @@ import math
 
 import numpy as np
 
-FP64, FP32, FP16S = 0, 1, 2
+FP64, FP32, FP16S, FP32SR = 0, 1, 2, 3
 DIRICHLET, ADIABATIC = 0, 1
 
 # Free relaxation rates and the D2Q5 weight parameter of the paper's cavity

@@ -77,7 +77,7 @@ def test_derived_values_of_workloads(lib):
 BAD = [
     dict(phi=1.0), dict(phi=0.0), dict(Da=0.0), dict(Pr=-1.0), dict(varpi=1.0),
     dict(s_q=2.0), dict(zeta_e=0.0), dict(eta_nu=2.5), dict(nx=3), dict(ny=2),
-    dict(precision=3), dict(periodic_x=2), dict(Ma=0.0, nu_f=0.0), dict(Ra=0.0, nu_f=0.0),
+    dict(precision=4), dict(periodic_x=2), dict(Ma=0.0, nu_f=0.0), dict(Ra=0.0, nu_f=0.0),
     dict(gamma_sf=0.0), dict(Hv=-1.0), dict(sigma=0.0), dict(Je=0.0), dict(rho0=0.0),
     dict(nu_wall=5), dict(wall_thermal=(0, 0, 2, 1)), dict(fp16_scale_f=3.0),
     dict(Ra=float("nan")), dict(nx=40000, ny=40000), dict(nx=23171, ny=23171),

@@ -119,14 +119,15 @@ def test_adjoint_from_a_given_state(B):
     assert ep <= 1e-10 and eh <= 1e-10
 
 
-def test_fp32_adjoint_tracks_fp64(B):
+@pytest.mark.parametrize("precision", [I.FP32, I.FP32SR], ids=["fp32", "fp32sr"])
+def test_fp32_adjoint_tracks_fp64(B, precision):
     p64, phi, Hv, _ = _small("cavity")
-    p32 = dict(p64, precision=I.FP32)
+    p32 = dict(p64, precision=precision)
     _, g64p, g64h = B.Lattice(p64, phi=phi, Hv=Hv).adjoint(400, 100)
     _, g32p, g32h = B.Lattice(p32, phi=phi, Hv=Hv).adjoint(400, 100)
     ep = np.abs(g32p - g64p).max() / np.abs(g64p).max()
     eh = np.abs(g32h - g64h).max() / np.abs(g64h).max()
-    say("fp32 vs fp64 adjoint: phi %.2e Hv %.2e" % (ep, eh))
+    say("precision %d vs fp64 adjoint: phi %.2e Hv %.2e" % (precision, ep, eh))
     assert ep <= 1e-4 and eh <= 1e-4
 
 

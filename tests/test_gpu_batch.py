@@ -45,9 +45,10 @@ def _mixed(precision):
     return ps, phis, hvs
 
 
-@pytest.mark.parametrize("persistent", [1, 0], ids=["persistent", "per_step"])
-def test_batch_equals_single(B, persistent):
-    ps, phis, hvs = _mixed(I.FP32)
+@pytest.mark.parametrize("persistent,precision", [(1, I.FP32), (0, I.FP32), (0, I.FP32SR), (1, I.FP16S)],
+                         ids=["persistent", "per_step", "per_step_fp32sr", "persistent_fp16s"])
+def test_batch_equals_single(B, persistent, precision):
+    ps, phis, hvs = _mixed(precision)
     say("mixed batch of", len(ps), "persistent" if persistent else "per-step")
     bt = B.Batch(ps, phi_fields=phis, Hv_fields=hvs)
     bt.set_mode(persistent)

@@ -124,11 +124,14 @@ def test_fp64_geometries(B, oracle, geom, fields):
     compare(g.macros(), o.macros(), 1e-12, GATED, "geom %s" % (geom,))
 
 
-def test_cavity_small_fp32_full_length(B, oracle):
-    say("cavity 64x64 fp32 2000 steps")
-    p = I.cavity_small(precision=I.FP32)
+@pytest.mark.parametrize("precision,tol", [(I.FP32, 1e-5), (I.FP32SR, 1e-6)], ids=["fp32", "fp32sr"])
+def test_cavity_small_fp32_full_length(B, oracle, precision, tol):
+    """binary32 storage, 2000 steps: binary32 arithmetic within 1e-5; binary64
+    arithmetic with stochastic rounding on store within 1e-6."""
+    say("cavity 64x64 precision", precision, "2000 steps")
+    p = I.cavity_small(precision=precision)
     g, o = pair(B, oracle, p, 2000)
-    compare(g.macros(), o.macros(), 1e-5, label="cavity_small fp32")
+    compare(g.macros(), o.macros(), tol, label="cavity_small precision %d" % precision)
 
 
 def test_cavity_large_fp32(B, oracle):
@@ -199,19 +202,26 @@ def test_throughput_fp32_strips(B, oracle):
     _strip_check(B, oracle, I.FP32, 50, 1e-5)
 
 
+def test_throughput_fp32sr_strips(B, oracle):
+    _strip_check(B, oracle, I.FP32SR, 50, 1e-6)
+
+
 def test_throughput_fp64_strips(B, oracle):
     _strip_check(B, oracle, I.FP64, 50, 1e-12, noise_floor=True)
 
 
 def test_throughput_fp16_error(B, oracle):
-    worst = _strip_check(B, oracle, I.FP16S, 50, 5e-2)
-    say("fp16 storage error after 50 steps (reported, not gated):", worst)
+    worst = _strip_check(B, oracle, I.FP16S, 50, 1e-2)
+    say("fp16 storage error after 50 steps:", worst)
 
 
 def test_fp16_cavity_error(B, oracle):
+    """binary16 storage with stochastic rounding, 2000 steps: the error is
+    reported; the bound only catches a broken form (round-to-nearest storage
+    gave 5e-2 here, stochastic rounding about 2e-3)."""
     p = I.cavity_small(precision=I.FP16S)
     g, o = pair(B, oracle, p, 2000)
-    compare(g.macros(), o.macros(), 0.2, label="cavity_small fp16 storage (reported)")
+    compare(g.macros(), o.macros(), 1e-2, label="cavity_small fp16 storage (reported)")
 
 
 def test_save_load_bitwise(B):
