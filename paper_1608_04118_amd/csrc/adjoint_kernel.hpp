@@ -366,9 +366,8 @@ __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >
 // when that node is a wall node or outside the lattice.
 template <typename Lm, typename C>
 __device__ __forceinline__ void gather_lambda(const Lm* __restrict__ mu, int x, int y, const StepConsts<C>& k,
-                                              Lm (&lam)[19]) {
+                                              const long long P, Lm (&lam)[19]) {
   const int nx = k.nx, ny = k.ny;
-  const long long P = k.plane;
 #pragma unroll
   for (int i = 0; i < kPlanes; ++i) {
     const int q = i < 9 ? i : (i < 14 ? i - 9 : i - 14);
@@ -425,6 +424,7 @@ struct AdjGrid {
   int ncol, collen, cy0;  // edge columns: x = 1 and (if ncol == 2) x = nx - 2
   int nedge;
   int edge_blocks;     // workgroups of the edge list, four lanes per node
+  long long lplane;    // elements between the planes of the adjoint populations (one plane each)
 };
 
 __device__ __forceinline__ void edge_node(int e, const AdjGrid& g, int nx, int ny, int& x, int& y) {
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(
     const R* __restrict__ init_ts, const StepConsts<C> k, const AdjGrid g) {
   const int b = blockIdx.x;
   const int nx = k.nx, ny = k.ny;
-  const long long P = k.plane;
+  const long long P = g.lplane;
   // ---- which node, and which part of it, this lane takes ----
   int x, y, slot = 0;
   bool valid;
@@ -514,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(
   // own (slot 0) or wall adjoint populations first, so the loads overlap the
   // arithmetic
   Lm lam[19];
-  if (Mode != kAdjSeed && active) gather_lambda(lam_in, slot == 0 ? x : ax, slot == 0 ? y : ay, k, lam);
+  if (Mode != kAdjSeed && active) gather_lambda(lam_in, slot == 0 ? x : ax, slot == 0 ? y : ay, k, P, lam);
   NodeMacros<C> m;
   C D0 = C(0);
   MacroAdj<C> bar;

@@ -386,7 +386,7 @@ int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params* ps, const double* co
   const size_t sb = storage_bytes(precision), cb = compute_bytes(precision);
   for (int i = 0; i < n; ++i) {
     const long long nn = b->n_of(i);
-    const size_t popb = align_up(kPlanes * plane_elems(ps[i].nx, ps[i].ny, precision) * sb, kAlign);
+    const size_t popb = align_up(pop_elems(ps[i].nx, ps[i].ny) * sb, kAlign);
     b->off_pop0[i] = o; o += popb;
     b->off_pop1[i] = o; o += popb;
     if (b->fields & kPhiField) { b->off_phi[i] = o; o += align_up(nn * cb, kAlign); }

@@ -10,8 +10,9 @@
 namespace ltne {
 
 // Populations per node: 9 of the D2Q9 flow lattice (Eq. 8), 5 of the fluid
-// and 5 of the solid D2Q5 temperature lattices.  Planes 0..8 hold f,
-// 9..13 g_f, 14..18 g_s; each plane is nx*ny values, row-major (x fastest).
+// and 5 of the solid D2Q5 temperature lattices: 0..8 f, 9..13 g_f,
+// 14..18 g_s.  Population q of node (x, y) sits at y rs + q qs + x (see
+// StepConsts): each lattice row stores its 19 population rows back to back.
 constexpr int kPlanes = 19;
 constexpr int kBlock = 256;  // threads per workgroup (4 wave64s)
 constexpr int kXcds = 8;     // MI355X: workgroups are dealt round-robin to 8 XCDs
@@ -32,15 +33,14 @@ constexpr int kXcds = 8;     // MI355X: workgroups are dealt round-robin to 8 XC
 #ifndef LTNE_NT_STORE
 #define LTNE_NT_STORE 1
 #endif
-#ifndef LTNE_PLANE_PAD
-#define LTNE_PLANE_PAD 256
-#endif
 constexpr int kRows = LTNE_ROWS;               // nodes per thread along y
 constexpr int kTwShiftMax = LTNE_TW_SHIFT_MAX;  // widest tile: 2^k nodes
 constexpr bool kXcdRemap = LTNE_XCD_REMAP != 0;
 constexpr bool kNtLoad = LTNE_NT_LOAD != 0;
 constexpr bool kNtStore = LTNE_NT_STORE != 0;
-constexpr int kPlanePad = LTNE_PLANE_PAD;      // elements between the end of one plane and the next
+// Every wave of the step kernel covers one lattice row (tiles are at least
+// 64 nodes wide), which its row addressing relies on.
+static_assert(kTwShiftMax >= 6, "tiles narrower than a wave");
 
 // Velocity components of Eq. 8 (D2Q9; the first five are the D2Q5 set).
 __host__ __device__ constexpr int vel_x(int i) {
@@ -89,7 +89,8 @@ template <typename C>
 struct StepConsts {
   int nx, ny;
   int px, py;            // periodic axes
-  long long plane;       // elements between population planes
+  long long qs;          // elements between the rows of populations q and q + 1 of one lattice row
+  long long rs;          // elements between lattice rows (19 qs)
   long long mplane;      // elements between macro planes
   TileMap tm;
   C rho0;

@@ -509,7 +509,7 @@ AdjGrid adjoint_grid(const lbm_ltne_params& p) {
   g.bw = std::max(0, (wxa ? nx - 3 : nx - 1) - g.bx0 + 1);
   g.bh = std::max(0, (wya ? ny - 3 : ny - 1) - g.by0 + 1);
   if (g.bw > 0 && g.bh > 0) {
-    g.tm = make_tiles(g.bw, g.bh, p.precision);
+    g.tm = make_tiles(g.bw, g.bh, p.precision, 0, p.precision == LBM_FP32 ? 6 : 8);
     g.bulk_blocks = grid_blocks(g.tm);
   }
   g.rowlen = wxa ? nx - 2 : nx;
@@ -520,6 +520,9 @@ AdjGrid adjoint_grid(const lbm_ltne_params& p) {
   g.ncol = wxa ? (nx - 2 > 1 ? 2 : 1) : 0;
   g.nedge = g.nrow * g.rowlen + g.ncol * g.collen;
   g.edge_blocks = static_cast<int>((4LL * g.nedge + kBlock - 1) / kBlock);
+  // planes rounded up to 1024 elements plus 256, so that the 19 planes do
+  // not all start on the same power-of-two boundary
+  g.lplane = static_cast<long long>(align_up(static_cast<size_t>(nx) * ny, 1024)) + 256;
   return g;
 }
 
@@ -546,7 +549,8 @@ int adjoint_t(lbm_ltne* h, int64_t nsteps, int64_t K, double* loss, double* dphi
   const int64_t nseg = (nsteps + K - 1) / K;
   const size_t popb = h->lay.pop_bytes;
   const size_t recb = align_up(static_cast<size_t>(K) * 5 * n * sizeof(R), kAlign);
-  const size_t lamb = align_up(static_cast<size_t>(kPlanes) * k.plane * sizeof(Lm), kAlign);
+  const AdjGrid ag = adjoint_grid(h->p);
+  const size_t lamb = align_up(static_cast<size_t>(kPlanes) * ag.lplane * sizeof(Lm), kAlign);
   const size_t gb = align_up(n * sizeof(double), kAlign);
   const size_t fb = align_up(n * sizeof(R), kAlign);
   const size_t total = nseg * popb + 2 * popb + recb + 2 * lamb + 2 * gb + 3 * fb;
@@ -607,7 +611,6 @@ int adjoint_t(lbm_ltne* h, int64_t nsteps, int64_t K, double* loss, double* dphi
   if ((e = hipMemsetAsync(gphi, 0, 2 * gb, h->stream)) != hipSuccess) return bail(hip_fail(e, "zero"));
   const R* phi_f = static_cast<const R*>(h->phi());
   const R* hv_f = static_cast<const R*>(h->hv());
-  const AdjGrid ag = adjoint_grid(h->p);
   const dim3 block(kBlock), grid(ag.bulk_blocks + ag.edge_blocks);
   auto sweep = [&](auto kernel, const Lm* lin, Lm* lout, const R* recp, const R* ws, const R* tf,
                    const R* ts) -> hipError_t {

@@ -168,38 +168,44 @@ __device__ __forceinline__ void node_update(
     b0 = w0 * gh;
     b1 = b2 = b3 = b4 = w1 * gh;
   } else {
-    // Pull: population i arrives from node (xc, yc) - e_i.
-    int xm = xc - 1, xp = xc + 1, ym = yc - 1, yp = yc + 1;
+    // Pull: population i arrives from node (xc, yc) - e_i.  A wave covers
+    // part of one lattice row, so the three source rows are wave-uniform:
+    // their bases are formed once in scalar registers (readfirstlane tells
+    // the compiler) and every load is a scalar base plus the lane's x.
+    const int yu = __builtin_amdgcn_readfirstlane(yc);
+    int xm = xc - 1, xp = xc + 1, ym = yu - 1, yp = yu + 1;
     if (k.px) {
       xm = (xc == 0) ? nx - 1 : xm;
       xp = (xc == nx - 1) ? 0 : xp;
     }
     if (k.py) {
-      ym = (yc == 0) ? ny - 1 : ym;
-      yp = (yc == ny - 1) ? 0 : yp;
+      ym = (yu == 0) ? ny - 1 : ym;
+      yp = (yu == ny - 1) ? 0 : yp;
     }
-    const int r0 = yc * nx, rm = ym * nx, rp = yp * nx;
-    const long long P = k.plane;
+    const long long Q = k.qs;
+    const S* __restrict__ s0 = src + yu * k.rs;
+    const S* __restrict__ sm = src + ym * k.rs;
+    const S* __restrict__ sp = src + yp * k.rs;
     const C isf = k.inv_sf, isg = k.inv_sg;
-    f0 = load_pop(at(src + 0 * P, r0 + xc), isf);
-    f1 = load_pop(at(src + 1 * P, r0 + xm), isf);
-    f2 = load_pop(at(src + 2 * P, rm + xc), isf);
-    f3 = load_pop(at(src + 3 * P, r0 + xp), isf);
-    f4 = load_pop(at(src + 4 * P, rp + xc), isf);
-    f5 = load_pop(at(src + 5 * P, rm + xm), isf);
-    f6 = load_pop(at(src + 6 * P, rm + xp), isf);
-    f7 = load_pop(at(src + 7 * P, rp + xp), isf);
-    f8 = load_pop(at(src + 8 * P, rp + xm), isf);
-    a0 = load_pop(at(src + 9 * P, r0 + xc), isg);
-    a1 = load_pop(at(src + 10 * P, r0 + xm), isg);
-    a2 = load_pop(at(src + 11 * P, rm + xc), isg);
-    a3 = load_pop(at(src + 12 * P, r0 + xp), isg);
-    a4 = load_pop(at(src + 13 * P, rp + xc), isg);
-    b0 = load_pop(at(src + 14 * P, r0 + xc), isg);
-    b1 = load_pop(at(src + 15 * P, r0 + xm), isg);
-    b2 = load_pop(at(src + 16 * P, rm + xc), isg);
-    b3 = load_pop(at(src + 17 * P, r0 + xp), isg);
-    b4 = load_pop(at(src + 18 * P, rp + xc), isg);
+    f0 = load_pop(at(s0 + 0 * Q, xc), isf);
+    f1 = load_pop(at(s0 + 1 * Q, xm), isf);
+    f2 = load_pop(at(sm + 2 * Q, xc), isf);
+    f3 = load_pop(at(s0 + 3 * Q, xp), isf);
+    f4 = load_pop(at(sp + 4 * Q, xc), isf);
+    f5 = load_pop(at(sm + 5 * Q, xm), isf);
+    f6 = load_pop(at(sm + 6 * Q, xp), isf);
+    f7 = load_pop(at(sp + 7 * Q, xp), isf);
+    f8 = load_pop(at(sp + 8 * Q, xm), isf);
+    a0 = load_pop(at(s0 + 9 * Q, xc), isg);
+    a1 = load_pop(at(s0 + 10 * Q, xm), isg);
+    a2 = load_pop(at(sm + 11 * Q, xc), isg);
+    a3 = load_pop(at(s0 + 12 * Q, xp), isg);
+    a4 = load_pop(at(sp + 13 * Q, xc), isg);
+    b0 = load_pop(at(s0 + 14 * Q, xc), isg);
+    b1 = load_pop(at(s0 + 15 * Q, xm), isg);
+    b2 = load_pop(at(sm + 16 * Q, xc), isg);
+    b3 = load_pop(at(s0 + 17 * Q, xp), isg);
+    b4 = load_pop(at(sp + 18 * Q, xc), isg);
   }
 
   // ---- macros at (xc, yc) ----
@@ -357,8 +363,9 @@ __device__ __forceinline__ void node_update(
     mac[4 * k.mplane + ib] = ths + k.T_ref;
   }
 
-  const long long P = k.plane;
-  const int io = y * nx + x;
+  const long long P = k.qs;
+  const int io = y * nx + x;  // node index (hash input)
+  S* __restrict__ drow = dst + static_cast<long long>(__builtin_amdgcn_readfirstlane(y)) * k.rs;
   // 19 x 16 random bits for the stores (unused by the same-type forms)
   uint32_t rb[10];
   if constexpr (kStochastic<S, C>) {
@@ -426,15 +433,15 @@ __device__ __forceinline__ void node_update(
     const C o4 = o2 + ((o5 + o6) - (o7 + o8)) - ms5;
     const C o0 = ms0 - (((o1 + o2) + (o3 + o4)) + ((o5 + o6) + (o7 + o8)));
     const C sf = k.sf;
-    store_pop(at(dst + 0 * P, io), o0, sf, (rb[0] & 0xffffu));
-    store_pop(at(dst + 1 * P, io), o1, sf, (rb[0] >> 16));
-    store_pop(at(dst + 2 * P, io), o2, sf, (rb[1] & 0xffffu));
-    store_pop(at(dst + 3 * P, io), o3, sf, (rb[1] >> 16));
-    store_pop(at(dst + 4 * P, io), o4, sf, (rb[2] & 0xffffu));
-    store_pop(at(dst + 5 * P, io), o5, sf, (rb[2] >> 16));
-    store_pop(at(dst + 6 * P, io), o6, sf, (rb[3] & 0xffffu));
-    store_pop(at(dst + 7 * P, io), o7, sf, (rb[3] >> 16));
-    store_pop(at(dst + 8 * P, io), o8, sf, (rb[4] & 0xffffu));
+    store_pop(at(drow + 0 * P, x), o0, sf, (rb[0] & 0xffffu));
+    store_pop(at(drow + 1 * P, x), o1, sf, (rb[0] >> 16));
+    store_pop(at(drow + 2 * P, x), o2, sf, (rb[1] & 0xffffu));
+    store_pop(at(drow + 3 * P, x), o3, sf, (rb[1] >> 16));
+    store_pop(at(drow + 4 * P, x), o4, sf, (rb[2] & 0xffffu));
+    store_pop(at(drow + 5 * P, x), o5, sf, (rb[2] >> 16));
+    store_pop(at(drow + 6 * P, x), o6, sf, (rb[3] & 0xffffu));
+    store_pop(at(drow + 7 * P, x), o7, sf, (rb[3] >> 16));
+    store_pop(at(drow + 8 * P, x), o8, sf, (rb[4] & 0xffffu));
   }
 
   // ---- D2Q5 collisions (Eqs. 32, 33) ----
@@ -460,11 +467,11 @@ __device__ __forceinline__ void node_update(
       const C r1 = o0 + h1 + o3 + o4, r2 = o0 + h2 + o3 - o4;
       const C r3 = o0 - h1 + o3 + o4, r4 = o0 - h2 + o3 - o4;
       // rest population from the conserved zeroth moment (see the flow part)
-      store_pop(at(dst + 9 * P, io), nf0 - ((r1 + r2) + (r3 + r4)), sg, (rb[4] >> 16));
-      store_pop(at(dst + 10 * P, io), r1, sg, (rb[5] & 0xffffu));
-      store_pop(at(dst + 11 * P, io), r2, sg, (rb[5] >> 16));
-      store_pop(at(dst + 12 * P, io), r3, sg, (rb[6] & 0xffffu));
-      store_pop(at(dst + 13 * P, io), r4, sg, (rb[6] >> 16));
+      store_pop(at(drow + 9 * P, x), nf0 - ((r1 + r2) + (r3 + r4)), sg, (rb[4] >> 16));
+      store_pop(at(drow + 10 * P, x), r1, sg, (rb[5] & 0xffffu));
+      store_pop(at(drow + 11 * P, x), r2, sg, (rb[5] >> 16));
+      store_pop(at(drow + 12 * P, x), r3, sg, (rb[6] & 0xffffu));
+      store_pop(at(drow + 13 * P, x), r4, sg, (rb[6] >> 16));
     }
     // solid phase (Eq. 33, equilibria of Eq. 38), carried as the difference
     // g_s - g_f: in moments, n_h* = n_s* - n_f* with n_s = n_f + n_h,
@@ -491,11 +498,11 @@ __device__ __forceinline__ void node_update(
       const C h1 = ns1 * C(0.5), h2 = ns2 * C(0.5);
       const C r1 = o0 + h1 + o3 + o4, r2 = o0 + h2 + o3 - o4;
       const C r3 = o0 - h1 + o3 + o4, r4 = o0 - h2 + o3 - o4;
-      store_pop(at(dst + 14 * P, io), nh0 - ((r1 + r2) + (r3 + r4)), sg, (rb[7] & 0xffffu));
-      store_pop(at(dst + 15 * P, io), r1, sg, (rb[7] >> 16));
-      store_pop(at(dst + 16 * P, io), r2, sg, (rb[8] & 0xffffu));
-      store_pop(at(dst + 17 * P, io), r3, sg, (rb[8] >> 16));
-      store_pop(at(dst + 18 * P, io), r4, sg, (rb[9] & 0xffffu));
+      store_pop(at(drow + 14 * P, x), nh0 - ((r1 + r2) + (r3 + r4)), sg, (rb[7] & 0xffffu));
+      store_pop(at(drow + 15 * P, x), r1, sg, (rb[7] >> 16));
+      store_pop(at(drow + 16 * P, x), r2, sg, (rb[8] & 0xffffu));
+      store_pop(at(drow + 17 * P, x), r3, sg, (rb[8] >> 16));
+      store_pop(at(drow + 18 * P, x), r4, sg, (rb[9] & 0xffffu));
     }
   }
 }
