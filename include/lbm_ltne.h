@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define LBM_LTNE_ABI_VERSION 1
+#define LBM_LTNE_ABI_VERSION 2
 
 /* Return codes. */
 #define LBM_OK 0
@@ -86,7 +86,7 @@ typedef struct lbm_ltne_params {
   int32_t periodic_y;      /* 1: periodic along y, 0: walls at y = 0 and y = ny-1 */
   int32_t wall_thermal[4]; /* LBM_WALL_* for walls 0..3 (ignored on periodic axes) */
   int32_t nu_wall;         /* wall of the reported Nusselt number; -1: hottest Dirichlet wall */
-  int32_t reserved0;
+  int32_t thermal_correction; /* 1: add the correction term of Sec. 3.2 to the fluid D2Q5 equation, 0: off */
   double T_wall[4];        /* Dirichlet temperature of walls 0..3 (both phases) */
   double T0;               /* Boussinesq reference temperature T_0 (Eq. 6) */
   double T_init_f, T_init_s; /* uniform initial temperatures when no field is given */
@@ -111,6 +111,9 @@ typedef struct lbm_ltne_params {
   double T_ref;            /* temperature shift reference of the FP32/FP16 forms; NaN: midpoint of the wall and initial temperatures */
   double fp16_scale_f;     /* power-of-two storage scale of shifted D2Q9 populations (LBM_FP16S); 0: automatic */
   double fp16_scale_g;     /* same for the D2Q5 populations; 0: automatic */
+  double pore_size;        /* D_p / L; > 0: h_v of every node from the correlation of Eq. 52 with the
+                              local Reynolds number |j| D_p / (rho nu_f) (Hv and an H_v field are then
+                              not used); 0: h_v from Hv or the H_v field */
 } lbm_ltne_params;
 
 /* Lattice values derived from a parameter set (uniform phi and H_v). */

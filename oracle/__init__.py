@@ -42,7 +42,7 @@ class _Params(C.Structure):
         ("nx", C.c_int32), ("ny", C.c_int32),
         ("periodic_x", C.c_int32), ("periodic_y", C.c_int32),
         ("wall_thermal", C.c_int32 * 4),
-        ("nu_wall", C.c_int32), ("pad_", C.c_int32),
+        ("nu_wall", C.c_int32), ("thermal_correction", C.c_int32),
         ("T_wall", C.c_double * 4),
         ("T0", C.c_double), ("T_init_f", C.c_double), ("T_init_s", C.c_double),
         ("L", C.c_double), ("dT", C.c_double),
@@ -55,7 +55,7 @@ class _Params(C.Structure):
         ("varpi", C.c_double), ("s_e", C.c_double), ("s_eps", C.c_double),
         ("s_q", C.c_double), ("zeta_e", C.c_double), ("zeta_nu", C.c_double),
         ("eta_e", C.c_double), ("eta_nu", C.c_double),
-        ("rho0", C.c_double),
+        ("rho0", C.c_double), ("pore_size", C.c_double),
     ]
 
 
@@ -65,7 +65,7 @@ class _Derived(C.Structure):
         "alpha_f", "alpha_s", "zeta_a", "eta_a", "K")]
 
 
-_ORACLE_KEYS = [f[0] for f in _Params._fields_ if f[0] != "pad_"]
+_ORACLE_KEYS = [f[0] for f in _Params._fields_]
 
 _lib = None
 

@@ -66,6 +66,9 @@ class DiffLattice:
     """One lattice in binary64 torch tensors; phi and Hv may require grad."""
 
     def __init__(self, p: dict, phi, Hv, Tf0=None, Ts0=None):
+        if int(p.get("thermal_correction", 0)) or float(p.get("pore_size", 0.0)) > 0.0:
+            raise NotImplementedError("the transcription covers the model without the "
+                                      "correction term and without the h_v correlation")
         self.p = dict(p)
         self.d = derive(p)
         self.nx, self.ny = int(p["nx"]), int(p["ny"])

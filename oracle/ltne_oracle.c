@@ -47,6 +47,24 @@
  *    belong to the same time as the state.
  *  - Per-cell porosity and interphase coefficient (an extension: the paper
  *    treats a homogeneous medium) enter every coefficient at the node.
+ *  - Interphase coefficient from the correlation of Eq. 52 (Sec. 4), when
+ *    pore_size = D_p / L > 0: H_p = h_v D_p^2 / k_f = 0.376 Re^0.644 Pr^0.37
+ *    with the local Reynolds number Re = u_m D_p / nu_f, i.e.
+ *    H_v = h_v L^2 / k_f = H_p / pore_size^2 at every node.  The paper calls
+ *    u_m the local average velocity; it is taken as |j| / rho with
+ *    j = sum_i e_i f_i the momentum the node's populations carry after
+ *    streaming (Eq. 18's companion first moment), because the velocity u of
+ *    Eq. 20 depends on T_f through the buoyancy, and T_f (Eqs. 43-46) in turn
+ *    on h_v: |j| / rho is the velocity of the same node and time that does
+ *    not close that loop (it differs from |u| by the half-step force
+ *    correction of Eq. 19, which is small where the buoyancy balances the
+ *    drag).  Wall nodes have u_b = 0 and hence h_v = 0; so has the fluid at
+ *    rest of the initial state.
+ *  - Correction term of Sec. 3.2 (flag thermal_correction): the fluid D2Q5
+ *    equation gains N^-1 (I - Q/2) C with C = N C~,
+ *    C~_i = w~_i T_f (e_i . F) / (phi cs_T^2), F the force of Eq. 5 of the
+ *    node (F_b at a wall node), added in moment space to the post-collision
+ *    moments.
  *  - Nusselt number (not defined in the paper): Nu = (L/dT) <-dT/dn> along the
  *    chosen wall, dT/dn from the one-sided second-order difference
  *    (-3T_0 + 4T_1 - T_2)/2, averaged with the trapezoid rule along a walled
@@ -291,6 +309,17 @@ static double cell_Fphi(const orc *o, double phi) {
   return 1.75 / sqrt(150.0 * phi * phi * phi); /* Ergun, Eq. 7 */
 }
 
+/* H_v = h_v L^2 / k_f of node c, whose local velocity is um: the given
+ * value, or the correlation of Eq. 52 with Re = um D_p / nu_f when a pore
+ * size is set (see the header). */
+static double node_Hv(const orc *o, int c, double um) {
+  if (!(o->p.pore_size > 0.0)) return o->Hv[c];
+  const double Dp = o->p.pore_size * o->d.L;  /* D_p in lattice units */
+  const double Re = um * Dp / o->d.nu_f;
+  const double Hp = 0.376 * pow(Re, 0.644) * pow(o->p.Pr, 0.37); /* Eq. 52 */
+  return Hp / (o->p.pore_size * o->p.pore_size);
+}
+
 /* d_0, d_1 of Eq. 46 with h_v/(rho c_p)_f = H_v alpha_f / L^2 (definition
  * of H_v, Sec. 2) and (rho c_p)_s = sigma (rho c_p)_f. */
 static void cell_d(const orc *o, double phi, double Hv, double *d0, double *d1) {
@@ -310,11 +339,16 @@ static void buoyancy(const orc *o, double Tf, double *Gx, double *Gy) {
 static void compute_macros(const orc *o, int c, const double *f, const double *gf,
                            const double *gs, node_macros *m) {
   const double phi = o->phi[c];
-  double d0, d1;
-  cell_d(o, phi, o->Hv[c], &d0, &d1);
-  /* Eq. 18 */
+  /* Eq. 18 and the first moment */
   double rho = 0.0;
   for (int i = 0; i < 9; ++i) rho += f[i];
+  double jx = 0.0, jy = 0.0;
+  for (int i = 0; i < 9; ++i) {
+    jx += EX[i] * f[i];
+    jy += EY[i] * f[i];
+  }
+  double d0, d1;
+  cell_d(o, phi, node_Hv(o, c, sqrt(jx * jx + jy * jy) / rho), &d0, &d1);
   /* Eqs. 43-46 */
   double sgf = 0.0, sgs = 0.0;
   for (int i = 0; i < 5; ++i) {
@@ -332,11 +366,6 @@ static void compute_macros(const orc *o, int c, const double *f, const double *g
   double Gx, Gy;
   buoyancy(o, Tf, &Gx, &Gy);
   /* Eq. 21 */
-  double jx = 0.0, jy = 0.0;
-  for (int i = 0; i < 9; ++i) {
-    jx += EX[i] * f[i];
-    jy += EY[i] * f[i];
-  }
   double vx = jx / rho + 0.5 * phi * Gx;
   double vy = jy / rho + 0.5 * phi * Gy;
   /* Eq. 22 */
@@ -394,6 +423,14 @@ static void collide(const orc *o, int c, const node_macros *m, const double *f,
   matvec5(N5, psi_v, psi);                              /* Eq. 29 */
   for (int k = 0; k < 5; ++k)
     ns[k] = n[k] - qf[k] * (n[k] - neq[k]) + (1.0 - 0.5 * qf[k]) * psi[k];
+  if (p->thermal_correction) {
+    /* correction term of Sec. 3.2: (I - Q/2) N C~ added to the moments */
+    double ct[5], cm[5];
+    for (int i = 0; i < 5; ++i)
+      ct[i] = wt[i] * m->Tf * (EX[i] * m->Fx + EY[i] * m->Fy) / (phi * o->d.csT2);
+    matvec5(N5, ct, cm);
+    for (int k = 0; k < 5; ++k) ns[k] += (1.0 - 0.5 * qf[k]) * cm[k];
+  }
   matvec5((const double(*)[5])N5inv, ns, gfo);
   /* solid phase */
   orc_geq_solid(m->Ts, p->varpi, geq);
@@ -451,7 +488,7 @@ static void initialize(orc *o, const double *Tf0, const double *Ts0) {
     double Tf = Tf0 ? Tf0[c] : o->p.T_init_f;
     double Ts = Ts0 ? Ts0[c] : o->p.T_init_s;
     double d0, d1;
-    cell_d(o, o->phi[c], o->Hv[c], &d0, &d1);
+    cell_d(o, o->phi[c], node_Hv(o, c, 0.0), &d0, &d1); /* fluid at rest */
     double Srf = 2.0 * d0 * (Ts - Tf) + o->p.Qf;
     double Srs = 2.0 * d1 * (Tf - Ts) + o->p.Qs;
     double geq[5];
@@ -573,7 +610,7 @@ static void boundaries_macros_collide(orc *o) {
         for (int i = 0; i < 5; ++i) gsb[i] = h0[i] + (o->gsp[cf * 5 + i] - h1[i]);
         /* prescribed macroscopic values of the wall node */
         double d0, d1, Gx, Gy;
-        cell_d(o, phib, o->Hv[c], &d0, &d1);
+        cell_d(o, phib, node_Hv(o, c, 0.0), &d0, &d1); /* u_b = 0 */
         buoyancy(o, Tfb, &Gx, &Gy);
         m.rho = mf.rho;
         m.ux = 0.0;

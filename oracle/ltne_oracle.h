@@ -14,7 +14,7 @@ typedef struct {
   int32_t periodic_x, periodic_y;
   int32_t wall_thermal[4]; /* left, right, bottom, top: 0 Dirichlet, 1 adiabatic */
   int32_t nu_wall;         /* wall for the Nusselt number, -1: hottest Dirichlet wall */
-  int32_t pad_;
+  int32_t thermal_correction; /* 1: add the correction term of Sec. 3.2 to the fluid D2Q5 equation */
   double T_wall[4];
   double T0;               /* Boussinesq reference temperature (Eq. 6) */
   double T_init_f, T_init_s;
@@ -27,6 +27,7 @@ typedef struct {
   double body_force[2];
   double varpi, s_e, s_eps, s_q, zeta_e, zeta_nu, eta_e, eta_nu;
   double rho0;
+  double pore_size;        /* D_p / L; > 0: h_v of every node from the correlation of Eq. 52 */
 } orc_params;
 
 typedef struct {

@@ -26,7 +26,7 @@ class lbm_ltne_params(C.Structure):
     _fields_ = [
         ("nx", C.c_int32), ("ny", C.c_int32), ("precision", C.c_int32),
         ("periodic_x", C.c_int32), ("periodic_y", C.c_int32),
-        ("wall_thermal", C.c_int32 * 4), ("nu_wall", C.c_int32), ("reserved0", C.c_int32),
+        ("wall_thermal", C.c_int32 * 4), ("nu_wall", C.c_int32), ("thermal_correction", C.c_int32),
         ("T_wall", C.c_double * 4), ("T0", C.c_double),
         ("T_init_f", C.c_double), ("T_init_s", C.c_double),
         ("L", C.c_double), ("dT", C.c_double),
@@ -40,6 +40,7 @@ class lbm_ltne_params(C.Structure):
         ("eta_e", C.c_double), ("eta_nu", C.c_double),
         ("rho0", C.c_double), ("T_ref", C.c_double),
         ("fp16_scale_f", C.c_double), ("fp16_scale_g", C.c_double),
+        ("pore_size", C.c_double),
     ]
 
 
@@ -149,7 +150,7 @@ def params_from_dict(d: dict) -> lbm_ltne_params:
 
 def params_to_dict(p: lbm_ltne_params) -> dict:
     return {k: (tuple(getattr(p, k)) if k in _ARRAY_KEYS else getattr(p, k))
-            for k, _ in lbm_ltne_params._fields_ if k != "reserved0"}
+            for k, _ in lbm_ltne_params._fields_}
 
 
 def _as_params(p) -> lbm_ltne_params:

@@ -37,7 +37,7 @@ static bool finite_all(const lbm_ltne_params* p) {
                       p->gamma_sf, p->sigma, p->Hv, p->Qf, p->Qs, p->Ma, p->nu_f,
                       p->body_force[0], p->body_force[1], p->varpi, p->s_e, p->s_eps, p->s_q,
                       p->zeta_e, p->zeta_nu, p->eta_e, p->eta_nu, p->rho0, p->fp16_scale_f,
-                      p->fp16_scale_g};
+                      p->fp16_scale_g, p->pore_size};
   for (double x : v)
     if (!std::isfinite(x)) return false;
   return true;
@@ -118,6 +118,11 @@ int derive(const lbm_ltne_params* p, double tmin, double tmax, lbm_ltne_derived*
     if (!rate_ok(rates[i])) return set_error(LBM_EINVAL, "%s = %g not in (0, 2)", names[i], rates[i]);
   if (!pow2_or_zero(p->fp16_scale_f) || !pow2_or_zero(p->fp16_scale_g))
     return set_error(LBM_EINVAL, "fp16 storage scales must be 0 or a power of two");
+  if (p->thermal_correction != 0 && p->thermal_correction != 1)
+    return set_error(LBM_EINVAL, "thermal_correction must be 0 or 1");
+  if (!(p->pore_size >= 0.0)) return set_error(LBM_EINVAL, "pore_size = %g must be >= 0", p->pore_size);
+  if (p->thermal_correction != 0 || p->pore_size > 0.0)
+    return set_error(LBM_EUNSUPPORTED, "the correction term and the h_v correlation are not built yet");
 
   d->cs2 = 1.0 / 3.0;
   d->csT2 = 0.5 * p->varpi;

@@ -35,7 +35,7 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 15
     for n in names:
         assert hasattr(lib, n), n
-    assert B.lbm_ltne_abi_version() == 1
+    assert B.lbm_ltne_abi_version() == 2
 
 
 def test_struct_layout_roundtrip(lib):
