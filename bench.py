@@ -5,8 +5,9 @@ heated from below (Ra = 1e5, Da = 1e-3, per-node porosity from seeded
 smoothed noise, seeded initial temperature noise), all three lattices fused
 into one launch per step.  The headline number is the FP32 form (shifted
 populations, binary32 arithmetic); the FP64, FP16-storage and FP32-storage /
-FP64-arithmetic (stochastic rounding) forms are timed on the same lattice and
-reported under "variants".
+FP64-arithmetic (stochastic rounding) forms, and the FP32 form with the
+Eq. 52 correlation and the Sec. 3.2 correction term, are timed on the same
+lattice and reported under "variants".
 
 A step is one launch of the fused kernel over the whole lattice.  Inputs are
 resident in device memory before timing starts.  The time of K steps is taken
@@ -39,8 +40,13 @@ WORKLOAD = ("porous layer 8192x8192, periodic x, walls y (bottom T=1, top T=0), 
             "initial T 0.5 +- 0.05")
 # Algorithmic HBM bytes per lattice-node update: 19 populations read and 19
 # written in the storage type, plus the per-node porosity in the compute type.
-BYTES_PER_LUP = {"f32": 19 * 4 * 2 + 4, "f64": 19 * 8 * 2 + 8, "f16s": 19 * 2 * 2 + 4, "f32sr": 19 * 4 * 2 + 8}
-PRECISION = {"f32": 1, "f64": 0, "f16s": 2, "f32sr": 3}
+BYTES_PER_LUP = {"f32": 19 * 4 * 2 + 4, "f64": 19 * 8 * 2 + 8, "f16s": 19 * 2 * 2 + 4, "f32sr": 19 * 4 * 2 + 8,
+                 "f32ext": 19 * 4 * 2 + 4}
+PRECISION = {"f32": 1, "f64": 0, "f16s": 2, "f32sr": 3, "f32ext": 1}
+# f32ext: the FP32 form with both model extensions on -- h_v of every node
+# from the correlation of Eq. 52 (D_p = 0.0135 L, the paper's pore size) and
+# the correction term of Sec. 3.2 -- at no extra memory traffic.
+EXTRA = {"f32ext": dict(thermal_correction=1, pore_size=0.0135)}
 KERNEL_SOURCES = ["paper_1608_04118_amd/csrc/step_kernel.hpp", "paper_1608_04118_amd/csrc/common.hpp",
                   "paper_1608_04118_amd/csrc/host_common.hpp", "paper_1608_04118_amd/csrc/lbm_ltne.hip",
                   "paper_1608_04118_amd/build.py"]
@@ -73,7 +79,7 @@ def time_form(tag: str, steps: int, warmup: int, inputs):
     import torch
     from paper_1608_04118_amd import binding as B
     p, phi, Tf0, Ts0 = inputs
-    p = dict(p, precision=PRECISION[tag])
+    p = dict(p, precision=PRECISION[tag], **EXTRA.get(tag, {}))
     lat = B.Lattice(p, phi=phi, Tf0=Tf0, Ts0=Ts0)
     stream = lat.stream
     if warmup:
@@ -261,7 +267,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--forms", default="f32,f64,f16s,f32sr")
+    ap.add_argument("--forms", default="f32,f64,f16s,f32sr,f32ext")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-cavity batch workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")

@@ -160,7 +160,9 @@ size_t lbm_ltne_pool_bytes(const lbm_ltne_params *p, int has_phi, int has_Hv);
  * collision of t = 0.
  *   phi_field, Hv_field, Tf_init, Ts_init: optional host arrays of nx*ny
  *     doubles (NULL: uniform p->phi, p->Hv, p->T_init_f, p->T_init_s);
- *     copied, the caller keeps ownership.  phi must lie in (0, 1), Hv >= 0.
+ *     copied, the caller keeps ownership.  phi must lie in (0, 1), Hv >= 0;
+ *     an Hv_field with p->pore_size > 0 (the correlation of Eq. 52) is
+ *     refused with LBM_EINVAL.
  *   hip_stream: a hipStream_t to queue all work on (borrowed; NULL: the
  *     default stream of the current device).
  *   device_pool, pool_bytes: optional caller-owned device memory of at least
@@ -222,7 +224,8 @@ int lbm_ltne_load(lbm_ltne_t h, const void *host_buf, size_t bytes);
  * per-node sums are recorded.  Work memory of about
  * (nsteps/ckpt_every + 2) state copies + 20 x ckpt_every bytes per node
  * (binary32) is allocated for the call.  FP64, FP32 and FP32SR forms
- * (LBM_EUNSUPPORTED for FP16 storage).  Synchronizes.  On an error the
+ * (LBM_EUNSUPPORTED for FP16 storage, and for a lattice with the correlation
+ * of Eq. 52 or the correction term of Sec. 3.2).  Synchronizes.  On an error the
  * lattice is left at its state on entry (unless the device itself failed).
  */
 int lbm_ltne_adjoint(lbm_ltne_t h, int64_t nsteps, int64_t ckpt_every, double *loss, double *dL_dphi,

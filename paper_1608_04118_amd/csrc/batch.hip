@@ -353,6 +353,8 @@ int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params* ps, const double* co
       for (long long j = 0; j < nn; ++j)
         if (!(phi_fields[i][j] > 0.0 && phi_fields[i][j] < 1.0))
           return set_error(LBM_EINVAL, "lattice %d: phi_field[%lld] not in (0, 1)", i, j);
+    if (Hv_fields && Hv_fields[i] && ps[i].pore_size > 0.0)
+      return set_error(LBM_EINVAL, "lattice %d: an H_v field and the correlation of Eq. 52 exclude each other", i);
     if (Hv_fields && Hv_fields[i])
       for (long long j = 0; j < nn; ++j)
         if (!(Hv_fields[i][j] >= 0.0) || !std::isfinite(Hv_fields[i][j]))

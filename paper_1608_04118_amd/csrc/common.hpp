@@ -113,6 +113,9 @@ struct StepConsts {
   C sf, inv_sf;          // storage scale of the shifted D2Q9 populations (1 unless FP16)
   C sg, inv_sg;          // same for the D2Q5 populations
   C theta_init_f, theta_init_s;  // uniform initial temperatures relative to T_ref
+  int hv_corr;           // 1: h_v of every node from the correlation of Eq. 52
+  C corr_a, corr_b;      // h_v / (rho c_p)_f = corr_a Re^0.644 with Re = corr_b |j| / rho
+  C tc;                  // 1 - zeta_alpha / 2 with the correction term of Sec. 3.2, else 0
 };
 
 }  // namespace ltne

@@ -134,6 +134,13 @@ inline void fill_step_consts(const lbm_ltne_params& p, const lbm_ltne_derived& d
   k->inv_sg = static_cast<C>(1.0 / d.scale_g);
   k->theta_init_f = static_cast<C>(p.T_init_f - d.T_ref);
   k->theta_init_s = static_cast<C>(p.T_init_s - d.T_ref);
+  // Eq. 52: H_p = h_v D_p^2 / k_f = 0.376 Re^0.644 Pr^0.37, Re = u_m D_p / nu_f,
+  // D_p = pore_size L, so h_v / (rho c_p)_f = H_p alpha_f / D_p^2
+  k->hv_corr = p.pore_size > 0.0 ? 1 : 0;
+  const double Dp = p.pore_size * d.L;
+  k->corr_a = static_cast<C>(k->hv_corr ? 0.376 * std::pow(p.Pr, 0.37) * d.alpha_f / (Dp * Dp) : 0.0);
+  k->corr_b = static_cast<C>(k->hv_corr ? Dp / d.nu_f : 0.0);
+  k->tc = static_cast<C>(p.thermal_correction ? 1.0 - 0.5 * d.zeta_a : 0.0);
 }
 
 inline int check_device(int* dev) {

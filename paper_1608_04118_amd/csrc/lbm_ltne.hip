@@ -183,6 +183,8 @@ int lbm_ltne_create(const lbm_ltne_params* p, const double* phi_field, const dou
     for (long long i = 0; i < n; ++i)
       if (!(phi_field[i] > 0.0 && phi_field[i] < 1.0))
         return set_error(LBM_EINVAL, "phi_field[%lld] = %g not in (0, 1)", i, phi_field[i]);
+  if (Hv_field && p->pore_size > 0.0)
+    return set_error(LBM_EINVAL, "an H_v field and the correlation of Eq. 52 (pore_size > 0) exclude each other");
   if (Hv_field)
     for (long long i = 0; i < n; ++i)
       if (!(Hv_field[i] >= 0.0) || !std::isfinite(Hv_field[i]))
@@ -689,6 +691,9 @@ extern "C" int lbm_ltne_adjoint(lbm_ltne_t h, int64_t nsteps, int64_t ckpt_every
   if (ckpt_every > nsteps) ckpt_every = nsteps;
   if (h->p.precision == LBM_FP16S)
     return set_error(LBM_EUNSUPPORTED, "the adjoint is built for the FP64, FP32 and FP32SR forms");
+  if (h->p.pore_size > 0.0 || h->p.thermal_correction)
+    return set_error(LBM_EUNSUPPORTED,
+                     "the adjoint covers the model without the correlation of Eq. 52 and the correction term");
   if (h->p.precision == LBM_FP64)
     return adjoint_t<double, double, double>(h, nsteps, ckpt_every, loss, dL_dphi, dL_dHv);
   if (h->p.precision == LBM_FP32SR)

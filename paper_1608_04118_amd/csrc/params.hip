@@ -121,8 +121,6 @@ int derive(const lbm_ltne_params* p, double tmin, double tmax, lbm_ltne_derived*
   if (p->thermal_correction != 0 && p->thermal_correction != 1)
     return set_error(LBM_EINVAL, "thermal_correction must be 0 or 1");
   if (!(p->pore_size >= 0.0)) return set_error(LBM_EINVAL, "pore_size = %g must be >= 0", p->pore_size);
-  if (p->thermal_correction != 0 || p->pore_size > 0.0)
-    return set_error(LBM_EUNSUPPORTED, "the correction term and the h_v correlation are not built yet");
 
   d->cs2 = 1.0 / 3.0;
   d->csT2 = 0.5 * p->varpi;

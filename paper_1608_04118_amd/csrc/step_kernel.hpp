@@ -123,6 +123,17 @@ __device__ __forceinline__ C dev_sqrt(C v) {
   }
 }
 
+// v^0.644 for v >= 0 (the Reynolds-number exponent of Eq. 52): exp2 of
+// 0.644 log2 v with the hardware log2 / exp2 in binary32, pow in binary64.
+template <typename C>
+__device__ __forceinline__ C pow_0644(C v) {
+  if constexpr (std::is_same<C, double>::value) {
+    return v > 0.0 ? pow(v, 0.644) : 0.0;
+  } else {
+    return v > 1e-30f ? __builtin_amdgcn_exp2f(0.644f * __builtin_amdgcn_logf(v)) : 0.0f;
+  }
+}
+
 // One node update: pull, macros, walls, collisions, store.  step numbers
 // the time step being computed (0: initialisation); with a narrow storage
 // form it seeds the stochastic rounding of the stores.
@@ -154,7 +165,7 @@ __device__ __forceinline__ void node_update(
     // g = w~ (T - Sr / 2), so that Eqs. 43-44 give back the initial T.
     const C thf = init_tf ? init_tf[ic] : k.theta_init_f;
     const C ths = init_ts ? init_ts[ic] : k.theta_init_s;
-    const C hv = hv_c * k.hvf;
+    const C hv = k.hv_corr ? C(0) : hv_c * k.hvf;  // the correlation gives 0 at rest
     const C d0 = C(0.5) * hv * dev_rcp(phi_c);
     const C d1 = C(0.5) * hv * k.inv_sigma * dev_rcp(C(1) - phi_c);
     const C srf = C(2) * d0 * (ths - thf) + k.Qf;
@@ -218,7 +229,19 @@ __device__ __forceinline__ void node_update(
   // themselves; on the difference lattice it is resolved to full relative
   // precision, and no carried sum is ever scaled by a rounded factor close
   // to 1 (a systematic drift in binary32 otherwise).
+  // Density (Eq. 18) and momentum sums.
+  const C drho = ((f0 + f1) + (f2 + f3)) + ((f4 + f5) + (f6 + f7)) + f8;
+  const C rho = k.rho0 + drho;
+  const C jx = (f1 - f3) + (f5 - f6) + (f8 - f7);
+  const C jy = (f2 - f4) + (f5 + f6) - (f7 + f8);
+  const C inv_rho = dev_rcp(rho);
+
   C hv = hv_c * k.hvf;  // h_v / (rho c_p)_f
+  if (k.hv_corr) {
+    // Eq. 52 with the local velocity u_m = |j| / rho (u of Eq. 20 needs T_f,
+    // which needs h_v): h_v / (rho c_p)_f = corr_a Re^0.644, Re = corr_b u_m
+    hv = k.corr_a * pow_0644(k.corr_b * dev_sqrt(jx * jx + jy * jy) * inv_rho);
+  }
   const C rphi_c = dev_rcp(phi_c);
   C d0 = C(0.5) * hv * rphi_c;
   C d1 = C(0.5) * hv * k.inv_sigma * dev_rcp(C(1) - phi_c);
@@ -228,12 +251,6 @@ __device__ __forceinline__ void node_update(
   C D = (sgh + C(0.5) * (k.Qs - k.Qf)) * dev_rcp(C(1) + d0 + d1);
   C thf = A + d0 * D;
   C ths = thf + D;
-
-  // Density (Eq. 18) and momentum sums.
-  const C drho = ((f0 + f1) + (f2 + f3)) + ((f4 + f5) + (f6 + f7)) + f8;
-  const C rho = k.rho0 + drho;
-  const C jx = (f1 - f3) + (f5 - f6) + (f8 - f7);
-  const C jy = (f2 - f4) + (f5 + f6) - (f7 + f8);
 
   if constexpr ((F & kRecord) != 0) {
     if (!wall) {
@@ -254,7 +271,6 @@ __device__ __forceinline__ void node_update(
   C ux, uy, rFx, rFy;
   {
     const C Fphi = (k.Fphi >= C(0)) ? k.Fphi : C(1.75) * dev_rsqrt(C(150) * phi_c * phi_c * phi_c);
-    const C inv_rho = dev_rcp(rho);
     const C vx = jx * inv_rho + C(0.5) * phi_c * Gx;
     const C vy = jy * inv_rho + C(0.5) * phi_c * Gy;
     const C l0 = C(0.5) * (C(1) + C(0.5) * phi_c * k.nu_over_K);
@@ -334,7 +350,8 @@ __device__ __forceinline__ void node_update(
     const int ib = y * nx + x;
     phi = (F & kPhiField) ? phi_field[ib] : k.phi_u;
     rphi = dev_rcp(phi);
-    const C hvb = ((F & kHvField) ? hv_field[ib] : k.hv_u) * k.hvf;
+    // (u = 0 at the wall: the correlation gives h_v = 0 there)
+    const C hvb = k.hv_corr ? C(0) : ((F & kHvField) ? hv_field[ib] : k.hv_u) * k.hvf;
     d0 = C(0.5) * hvb * rphi;
     d1 = C(0.5) * hvb * k.inv_sigma * dev_rcp(C(1) - phi);
     thf = thfb;
@@ -450,13 +467,18 @@ __device__ __forceinline__ void node_update(
     const C ip = rphi;
     const C Tf = thf + k.T_ref;
     const C sg = k.sg;
+    // correction term of Sec. 3.2 in moments: (1 - zeta_a / 2) T_f F / phi
+    // added to the post-collision heat flux of the fluid lattice (tc = 0
+    // when the term is off); F = rho F / rho, the node's force of Eq. 5
+    const C tcf = k.tc * Tf * ip * inv_rho;
+    const C cx = tcf * rFx, cy = tcf * rFy;
     // fluid phase, equilibria of Eq. 37, source moments (Sr, 0, 0, c1 Sr, 0)
     {
       const C n1 = a1 - a3, n2 = a2 - a4;
       const C n3 = C(-4) * a0 + ((a1 + a2) + (a3 + a4));
       const C n4 = (a1 - a2) + (a3 - a4);
-      const C ns1 = n1 - k.z_a * (n1 - ux * Tf * ip);
-      const C ns2 = n2 - k.z_a * (n2 - uy * Tf * ip);
+      const C ns1 = (n1 - k.z_a * (n1 - ux * Tf * ip)) + cx;
+      const C ns2 = (n2 - k.z_a * (n2 - uy * Tf * ip)) + cy;
       const C ns3 = n3 - k.z_e * (n3 - c1 * thf) + (C(1) - C(0.5) * k.z_e) * c1 * srf;
       const C ns4 = n4 - k.z_nu * n4;
       // g* = N^{-1} n*, N^{-1} = N^T diag(1/5, 1/2, 1/2, 1/20, 1/4)
@@ -475,7 +497,8 @@ __device__ __forceinline__ void node_update(
     }
     // solid phase (Eq. 33, equilibria of Eq. 38), carried as the difference
     // g_s - g_f: in moments, n_h* = n_s* - n_f* with n_s = n_f + n_h,
-    //   n_h1* = (1 - eta_a) n_h1 + (zeta_a - eta_a) n_f1 - zeta_a u_x T_f / phi,
+    //   n_h1* = (1 - eta_a) n_h1 + (zeta_a - eta_a) n_f1 - zeta_a u_x T_f / phi
+    //           (minus the fluid's correction term when it is on),
     //   n_h3* = (1 - eta_e) n_h3 + (zeta_e - eta_e)(n_f3 - c1 T_f) + c1 eta_e D
     //           + c1 [(1 - eta_e / 2) Sr_s - (1 - zeta_e / 2) Sr_f],
     //   n_h4* = (1 - eta_nu) n_h4 + (zeta_nu - eta_nu) n_f4,
@@ -487,8 +510,8 @@ __device__ __forceinline__ void node_update(
       const C n1 = b1 - b3, n2 = b2 - b4;
       const C n3 = C(-4) * b0 + ((b1 + b2) + (b3 + b4));
       const C n4 = (b1 - b2) + (b3 - b4);
-      const C ns1 = (C(1) - k.e_a) * n1 + ((k.z_a - k.e_a) * nf1 - k.z_a * ux * Tf * ip);
-      const C ns2 = (C(1) - k.e_a) * n2 + ((k.z_a - k.e_a) * nf2 - k.z_a * uy * Tf * ip);
+      const C ns1 = ((C(1) - k.e_a) * n1 + ((k.z_a - k.e_a) * nf1 - k.z_a * ux * Tf * ip)) - cx;
+      const C ns2 = ((C(1) - k.e_a) * n2 + ((k.z_a - k.e_a) * nf2 - k.z_a * uy * Tf * ip)) - cy;
       const C ns3 = (C(1) - k.e_e) * n3 + (k.z_e - k.e_e) * (nf3 - c1 * thf) +
                     c1 * (k.e_e * D + ((C(1) - C(0.5) * k.e_e) * srs - (C(1) - C(0.5) * k.z_e) * srf));
       const C ns4 = (C(1) - k.e_nu) * n4 + (k.z_nu - k.e_nu) * nf4;

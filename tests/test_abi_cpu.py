@@ -81,6 +81,7 @@ BAD = [
     dict(gamma_sf=0.0), dict(Hv=-1.0), dict(sigma=0.0), dict(Je=0.0), dict(rho0=0.0),
     dict(nu_wall=5), dict(wall_thermal=(0, 0, 2, 1)), dict(fp16_scale_f=3.0),
     dict(Ra=float("nan")), dict(nx=40000, ny=40000), dict(nx=23171, ny=23171),
+    dict(thermal_correction=2), dict(pore_size=-0.01), dict(pore_size=float("inf")),
 ]
 
 
@@ -127,6 +128,10 @@ def test_create_rejects_before_touching_a_device(lib):
     with pytest.raises(B.LtneError) as e:
         B.lbm_ltne_create(I.cavity_small(), phi_field=bad_phi)
     assert e.value.code in (B.LBM_EINVAL, B.LBM_ENODEV)
+    # an H_v field and the correlation of Eq. 52 exclude each other
+    with pytest.raises(B.LtneError) as e:
+        B.lbm_ltne_create(I.cavity_small(pore_size=0.0135), Hv_field=np.full(64 * 64, 10.0))
+    assert e.value.code == B.LBM_EINVAL
 
 
 def test_null_handles_are_refused(lib):

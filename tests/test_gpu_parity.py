@@ -153,7 +153,7 @@ def test_channel_fp32(B, oracle):
 
 
 def _strip_check(B, oracle, precision, steps, tol, windows=((0, 16), (4000, 16), (8176, 16)),
-                 noise_floor=False):
+                 noise_floor=False, **extra):
     """GPU run of the full 8192 x 8192 layer; oracle runs of periodic strips
     around the windows.  Errors are relative to the field's magnitude over the
     whole lattice (velocity as a vector).  With noise_floor, the gate is
@@ -161,8 +161,8 @@ def _strip_check(B, oracle, precision, steps, tol, windows=((0, 16), (4000, 16),
     its inputs), for fields so small after few steps that tol lies below what
     binary64 populations of size 0.1 resolve."""
     n = 8192
-    p, phi, Tf0, Ts0 = I.throughput(n=n, precision=precision)
-    say("throughput 8192x8192 precision", precision, "steps", steps)
+    p, phi, Tf0, Ts0 = I.throughput(n=n, precision=precision, **extra)
+    say("throughput 8192x8192 precision", precision, "steps", steps, extra)
     g = B.Lattice(p, phi=phi, Tf0=Tf0, Ts0=Ts0).step(steps)
     gm = g.macros()
     g.close()
