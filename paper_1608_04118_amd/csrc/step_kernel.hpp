@@ -61,34 +61,60 @@ __device__ __forceinline__ void store_raw(S* __restrict__ p, S v) {
   }
 }
 
-// Storage forms narrower than the arithmetic round stochastically: r16
-// (16 random bits) is added below the kept significand bits, which are then
-// truncated, so a value is rounded up with probability equal to its distance
-// from the lower neighbour in units of the last place.  The expected stored
-// value is the exact one: rounding errors no longer repeat themselves step
-// after step on a slowly changing field (where round-to-nearest would add
-// the same error at every step), they average out.
+// Storage forms narrower than the arithmetic round stochastically: random
+// bits are added below the kept significand bits, which are then truncated,
+// so a value is rounded up with probability equal to its distance from the
+// lower neighbour in units of the last place.  The expected stored value is
+// the exact one: rounding errors no longer repeat themselves step after step
+// on a slowly changing field (where round-to-nearest would add the same
+// error at every step), they average out.  r carries the random bits in its
+// top 16 bits (the low 16 bits are ignored).
 template <typename S, typename C>
 constexpr bool kStochastic = !std::is_same<S, C>::value;
 
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
 template <typename S, typename C>
-__device__ __forceinline__ void store_pop(S* __restrict__ p, C v, C scale, uint32_t r16) {
+__device__ __forceinline__ void store_pop(S* __restrict__ p, C v, C scale, uint32_t r) {
   if constexpr (std::is_same<S, _Float16>::value) {
-    // binary32 -> binary16: 13 discarded significand bits
-    uint32_t u = __float_as_uint(static_cast<float>(v * scale)) + (r16 >> 3);
-    u &= ~0x1fffu;
-    store_raw(p, static_cast<_Float16>(__uint_as_float(u)));  // exact for normal binary16 values
+    // binary32 -> binary16: the gfx950 stochastic-rounding convert adds the
+    // top 13 bits of r to the 13 discarded significand bits
+    half2_t h = __builtin_nondeterministic_value(h);
+    h = __builtin_amdgcn_cvt_sr_f16_f32(h, static_cast<float>(v * scale), r, false);
+    store_raw(p, h[0]);
   } else if constexpr (std::is_same<S, float>::value && std::is_same<C, double>::value) {
-    // binary64 -> binary32: 29 discarded significand bits
+    // binary64 -> binary32: 29 discarded significand bits, 16 random ones
+    // added at their top
     (void)scale;
     unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v)) +
-                           (static_cast<unsigned long long>(r16) << 13);
+                           (static_cast<unsigned long long>(r >> 16) << 13);
     u &= ~0x1fffffffull;
     store_raw(p, static_cast<float>(__longlong_as_double(static_cast<long long>(u))));  // exact
   } else {
     (void)scale;
-    (void)r16;
+    (void)r;
     store_raw(p, static_cast<S>(v));
+  }
+}
+
+// Two stores that share one random word w: the first value takes its bottom
+// half (moved to the top), the second its top half.  In binary16 both go
+// through the gfx950 stochastic-rounding convert, which adds the top 13
+// bits of its random operand to the 13 discarded significand bits, into the
+// two halves of one register (h carries that register from pair to pair, so
+// no register is cleared for it).
+template <typename S, typename C>
+__device__ __forceinline__ void store_pair(S* __restrict__ pa, C va, C sa, S* __restrict__ pb, C vb, C sb,
+                                           uint32_t w, half2_t& h) {
+  if constexpr (std::is_same<S, _Float16>::value) {
+    h = __builtin_amdgcn_cvt_sr_f16_f32(h, static_cast<float>(va * sa), w << 16, false);
+    h = __builtin_amdgcn_cvt_sr_f16_f32(h, static_cast<float>(vb * sb), w, true);
+    store_raw(pa, h[0]);
+    store_raw(pb, h[1]);
+  } else {
+    (void)h;
+    store_pop(pa, va, sa, w << 16);
+    store_pop(pb, vb, sb, w);
   }
 }
 
@@ -383,7 +409,8 @@ __device__ __forceinline__ void node_update(
   const long long P = k.qs;
   const int io = y * nx + x;  // node index (hash input)
   S* __restrict__ drow = dst + static_cast<long long>(__builtin_amdgcn_readfirstlane(y)) * k.rs;
-  // 19 x 16 random bits for the stores (unused by the same-type forms)
+  // 19 x 16 random bits for the stores, two stores per word (its top and
+  // its bottom half moved to the top); unused by the same-type forms
   uint32_t rb[10];
   if constexpr (kStochastic<S, C>) {
     const uint32_t base = mix32(static_cast<uint32_t>(io) ^ mix32(step * 0x9e3779b9u + 0x632be5abu));
@@ -394,6 +421,8 @@ __device__ __forceinline__ void node_update(
     for (int j = 0; j < 10; ++j) rb[j] = 0u;
   }
 
+  half2_t hs = __builtin_nondeterministic_value(hs);  // binary16 store register (see store_pair)
+  C f8_out;
   // ---- D2Q9 collision in moment space (Eq. 10) ----
   {
     const C ip = rphi;
@@ -450,15 +479,11 @@ __device__ __forceinline__ void node_update(
     const C o4 = o2 + ((o5 + o6) - (o7 + o8)) - ms5;
     const C o0 = ms0 - (((o1 + o2) + (o3 + o4)) + ((o5 + o6) + (o7 + o8)));
     const C sf = k.sf;
-    store_pop(at(drow + 0 * P, x), o0, sf, (rb[0] & 0xffffu));
-    store_pop(at(drow + 1 * P, x), o1, sf, (rb[0] >> 16));
-    store_pop(at(drow + 2 * P, x), o2, sf, (rb[1] & 0xffffu));
-    store_pop(at(drow + 3 * P, x), o3, sf, (rb[1] >> 16));
-    store_pop(at(drow + 4 * P, x), o4, sf, (rb[2] & 0xffffu));
-    store_pop(at(drow + 5 * P, x), o5, sf, (rb[2] >> 16));
-    store_pop(at(drow + 6 * P, x), o6, sf, (rb[3] & 0xffffu));
-    store_pop(at(drow + 7 * P, x), o7, sf, (rb[3] >> 16));
-    store_pop(at(drow + 8 * P, x), o8, sf, (rb[4] & 0xffffu));
+    store_pair(at(drow + 0 * P, x), o0, sf, at(drow + 1 * P, x), o1, sf, rb[0], hs);
+    store_pair(at(drow + 2 * P, x), o2, sf, at(drow + 3 * P, x), o3, sf, rb[1], hs);
+    store_pair(at(drow + 4 * P, x), o4, sf, at(drow + 5 * P, x), o5, sf, rb[2], hs);
+    store_pair(at(drow + 6 * P, x), o6, sf, at(drow + 7 * P, x), o7, sf, rb[3], hs);
+    f8_out = o8;  // stored with the first thermal population, sharing its random word
   }
 
   // ---- D2Q5 collisions (Eqs. 32, 33) ----
@@ -489,11 +514,10 @@ __device__ __forceinline__ void node_update(
       const C r1 = o0 + h1 + o3 + o4, r2 = o0 + h2 + o3 - o4;
       const C r3 = o0 - h1 + o3 + o4, r4 = o0 - h2 + o3 - o4;
       // rest population from the conserved zeroth moment (see the flow part)
-      store_pop(at(drow + 9 * P, x), nf0 - ((r1 + r2) + (r3 + r4)), sg, (rb[4] >> 16));
-      store_pop(at(drow + 10 * P, x), r1, sg, (rb[5] & 0xffffu));
-      store_pop(at(drow + 11 * P, x), r2, sg, (rb[5] >> 16));
-      store_pop(at(drow + 12 * P, x), r3, sg, (rb[6] & 0xffffu));
-      store_pop(at(drow + 13 * P, x), r4, sg, (rb[6] >> 16));
+      store_pair(at(drow + 8 * P, x), f8_out, k.sf, at(drow + 9 * P, x), nf0 - ((r1 + r2) + (r3 + r4)), sg,
+                 rb[4], hs);
+      store_pair(at(drow + 10 * P, x), r1, sg, at(drow + 11 * P, x), r2, sg, rb[5], hs);
+      store_pair(at(drow + 12 * P, x), r3, sg, at(drow + 13 * P, x), r4, sg, rb[6], hs);
     }
     // solid phase (Eq. 33, equilibria of Eq. 38), carried as the difference
     // g_s - g_f: in moments, n_h* = n_s* - n_f* with n_s = n_f + n_h,
@@ -521,11 +545,10 @@ __device__ __forceinline__ void node_update(
       const C h1 = ns1 * C(0.5), h2 = ns2 * C(0.5);
       const C r1 = o0 + h1 + o3 + o4, r2 = o0 + h2 + o3 - o4;
       const C r3 = o0 - h1 + o3 + o4, r4 = o0 - h2 + o3 - o4;
-      store_pop(at(drow + 14 * P, x), nh0 - ((r1 + r2) + (r3 + r4)), sg, (rb[7] & 0xffffu));
-      store_pop(at(drow + 15 * P, x), r1, sg, (rb[7] >> 16));
-      store_pop(at(drow + 16 * P, x), r2, sg, (rb[8] & 0xffffu));
-      store_pop(at(drow + 17 * P, x), r3, sg, (rb[8] >> 16));
-      store_pop(at(drow + 18 * P, x), r4, sg, (rb[9] & 0xffffu));
+      store_pair(at(drow + 14 * P, x), nh0 - ((r1 + r2) + (r3 + r4)), sg, at(drow + 15 * P, x), r1, sg, rb[7],
+                 hs);
+      store_pair(at(drow + 16 * P, x), r2, sg, at(drow + 17 * P, x), r3, sg, rb[8], hs);
+      store_pop(at(drow + 18 * P, x), r4, sg, (rb[9] << 16));
     }
   }
 }
