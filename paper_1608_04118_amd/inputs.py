@@ -19,6 +19,8 @@ Workloads (the paper uses no public dataset; every workload is synthetic):
 * ``batch``          -- 256 cavities of uneven size and parameters.
 * ``adjoint_cavity`` -- 512 x 512 cavity with seeded porosity and interphase
                         coefficient fields.
+* ``paper_cavity``   -- the cavity of the paper's own runs (Sec. 4), h_v from
+                        the correlation of Eq. 52.
 """
 from __future__ import annotations
 
@@ -183,6 +185,21 @@ def adjoint_cavity(n: int = 512, precision: int = FP32, **kw):
     phi = np.clip(0.65 + 0.1 * smoothed_noise(6, n, n), 0.4, 0.9)
     Hv = 10.0 * (1.0 + 0.5 * np.clip(smoothed_noise(7, n, n), -1.0, 1.0))
     return p, phi, Hv
+
+
+def paper_cavity(n: int = 128, Ra: float = 1e6, pore_size: float = 0.0135, **kw) -> dict:
+    """The cavity of the paper's own runs (Sec. 4): n x n nodes, hot left wall
+    T_h = 11, cold right wall T_c = T_0 = 1 (dT = 10), adiabatic top and
+    bottom, fluid and solid initially at T_0; phi = 0.8, Da = 1e-4,
+    F_phi = 0.068, Pr = 1, J_e = 1, sigma = 1, gamma_sf = 1000, and h_v from
+    the correlation of Eq. 52 with D_p = 0.0135 L (pore_size = 0: no
+    interphase exchange, the H_p = 0 case).  FP64 unless overridden."""
+    base = dict(nx=n, ny=n, precision=FP64, T_wall=(11.0, 1.0, 0.0, 0.0), T0=1.0, T_init_f=1.0,
+                T_init_s=1.0, wall_thermal=(DIRICHLET, DIRICHLET, ADIABATIC, ADIABATIC), phi=0.8,
+                Da=1e-4, F_phi=0.068, Ra=Ra, Pr=1.0, Je=1.0, gamma_sf=1000.0, sigma=1.0, Hv=0.0,
+                pore_size=pore_size)
+    base.update(kw)
+    return complete(**base)
 
 
 def fd_cells(n: int = 512, count: int = 32, seed: int = 8):
