@@ -221,9 +221,12 @@ int lbm_ltne_load(lbm_ltne_t h, const void *host_buf, size_t bytes);
  * the wall reconstruction and, when the handle is still at t = 0, the
  * initialisation.  Checkpoints of the state are kept every ckpt_every steps
  * (< 1: one segment) and each segment is recomputed once while its
- * per-node sums are recorded.  Work memory of about
- * (nsteps/ckpt_every + 2) state copies + 20 x ckpt_every bytes per node
- * (binary32) is allocated for the call.  FP64, FP32 and FP32SR forms
+ * per-node sums are recorded, on a second stream of the library's own that
+ * runs the recompute of one segment while the handle's stream sweeps the
+ * next one back.  Work memory of about (nsteps/ckpt_every + 2) state copies
+ * + 40 x ckpt_every bytes per node (binary32; two recording buffers, or one
+ * with 20 x ckpt_every bytes per node when two do not fit, and then the
+ * recompute and the sweep alternate) is allocated for the call.  FP64, FP32 and FP32SR forms
  * (LBM_EUNSUPPORTED for FP16 storage, and for a lattice with the correlation
  * of Eq. 52 or the correction term of Sec. 3.2).  Synchronizes.  On an error the
  * lattice is left at its state on entry (unless the device itself failed).

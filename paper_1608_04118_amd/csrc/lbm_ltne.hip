@@ -51,9 +51,10 @@ void fill_consts(const lbm_ltne* h, StepConsts<C>* k) {
 
 template <typename S, typename C, int F>
 hipError_t launch_one(const lbm_ltne* h, const StepConsts<C>& k, uint32_t step, const void* src, void* dst,
-                      void* mac, const void* init_tf, const void* init_ts, void* rec = nullptr) {
+                      void* mac, const void* init_tf, const void* init_ts, void* rec = nullptr,
+                      hipStream_t stream = nullptr) {
   const dim3 grid(grid_blocks(k.tm)), block(kBlock);
-  hipLaunchKernelGGL((step_kernel<S, C, F>), grid, block, 0, h->stream,
+  hipLaunchKernelGGL((step_kernel<S, C, F>), grid, block, 0, stream ? stream : h->stream,
                      static_cast<const S*>(src), static_cast<S*>(dst),
                      static_cast<const C*>(h->phi()), static_cast<const C*>(h->hv()),
                      static_cast<C*>(mac), static_cast<const C*>(init_tf),
@@ -67,27 +68,27 @@ hipError_t launch_one(const lbm_ltne* h, const StepConsts<C>& k, uint32_t step, 
 template <typename S, typename C>
 hipError_t launch_step_t(const lbm_ltne* h, const StepConsts<C>& k, int mode, uint32_t step, const void* src,
                          void* dst, void* mac, const void* init_tf, const void* init_ts,
-                         void* rec) {
+                         void* rec, hipStream_t stream) {
   const int fl = (h->has_phi ? kPhiField : 0) | (h->has_hv ? kHvField : 0);
   if constexpr (!std::is_same<S, _Float16>::value) {
     if (mode == 3 || mode == 4) {
       switch (fl) {
         case 0:
-          return mode == 3 ? launch_one<S, C, kRecord>(h, k, step, src, dst, mac, init_tf, init_ts, rec)
-                           : launch_one<S, C, kRecord | kMacros>(h, k, step, src, dst, mac, init_tf, init_ts, rec);
+          return mode == 3 ? launch_one<S, C, kRecord>(h, k, step, src, dst, mac, init_tf, init_ts, rec, stream)
+                           : launch_one<S, C, kRecord | kMacros>(h, k, step, src, dst, mac, init_tf, init_ts, rec, stream);
         case kPhiField:
-          return mode == 3 ? launch_one<S, C, kPhiField | kRecord>(h, k, step, src, dst, mac, init_tf, init_ts, rec)
+          return mode == 3 ? launch_one<S, C, kPhiField | kRecord>(h, k, step, src, dst, mac, init_tf, init_ts, rec, stream)
                            : launch_one<S, C, kPhiField | kRecord | kMacros>(h, k, step, src, dst, mac, init_tf,
-                                                                            init_ts, rec);
+                                                                            init_ts, rec, stream);
         case kHvField:
-          return mode == 3 ? launch_one<S, C, kHvField | kRecord>(h, k, step, src, dst, mac, init_tf, init_ts, rec)
+          return mode == 3 ? launch_one<S, C, kHvField | kRecord>(h, k, step, src, dst, mac, init_tf, init_ts, rec, stream)
                            : launch_one<S, C, kHvField | kRecord | kMacros>(h, k, step, src, dst, mac, init_tf,
-                                                                           init_ts, rec);
+                                                                           init_ts, rec, stream);
         default:
           return mode == 3
-                     ? launch_one<S, C, kPhiField | kHvField | kRecord>(h, k, step, src, dst, mac, init_tf, init_ts, rec)
+                     ? launch_one<S, C, kPhiField | kHvField | kRecord>(h, k, step, src, dst, mac, init_tf, init_ts, rec, stream)
                      : launch_one<S, C, kPhiField | kHvField | kRecord | kMacros>(h, k, step, src, dst, mac, init_tf,
-                                                                                 init_ts, rec);
+                                                                                 init_ts, rec, stream);
       }
     }
   } else {
@@ -96,9 +97,10 @@ hipError_t launch_step_t(const lbm_ltne* h, const StepConsts<C>& k, int mode, ui
   }
 #define LTNE_CASE(FL)                                                                               \
   case FL:                                                                                          \
-    if (mode == 0) return launch_one<S, C, FL>(h, k, step, src, dst, mac, init_tf, init_ts);               \
-    if (mode == 1) return launch_one<S, C, FL | kMacros>(h, k, step, src, dst, mac, init_tf, init_ts);     \
-    return launch_one<S, C, FL | kMacros | kInit>(h, k, step, src, dst, mac, init_tf, init_ts);
+    if (mode == 0) return launch_one<S, C, FL>(h, k, step, src, dst, mac, init_tf, init_ts, nullptr, stream); \
+    if (mode == 1)                                                                                  \
+      return launch_one<S, C, FL | kMacros>(h, k, step, src, dst, mac, init_tf, init_ts, nullptr, stream);  \
+    return launch_one<S, C, FL | kMacros | kInit>(h, k, step, src, dst, mac, init_tf, init_ts, nullptr, stream);
   switch (fl) {
     LTNE_CASE(0)
     LTNE_CASE(kPhiField)
@@ -112,17 +114,18 @@ hipError_t launch_step_t(const lbm_ltne* h, const StepConsts<C>& k, int mode, ui
 // step: the number of the time step being computed (0 for the
 // initialisation), the counter of the stochastic rounding.
 hipError_t launch_step(const lbm_ltne* h, int mode, int64_t step, const void* src, void* dst, void* mac,
-                       const void* init_tf, const void* init_ts, void* rec = nullptr) {
+                       const void* init_tf, const void* init_ts, void* rec = nullptr,
+                       hipStream_t stream = nullptr) {
   const uint32_t st = static_cast<uint32_t>(step);
   switch (h->p.precision) {
     case LBM_FP64:
-      return launch_step_t<double, double>(h, h->kd, mode, st, src, dst, mac, init_tf, init_ts, rec);
+      return launch_step_t<double, double>(h, h->kd, mode, st, src, dst, mac, init_tf, init_ts, rec, stream);
     case LBM_FP32:
-      return launch_step_t<float, float>(h, h->kf, mode, st, src, dst, mac, init_tf, init_ts, rec);
+      return launch_step_t<float, float>(h, h->kf, mode, st, src, dst, mac, init_tf, init_ts, rec, stream);
     case LBM_FP32SR:
-      return launch_step_t<float, double>(h, h->kd, mode, st, src, dst, mac, init_tf, init_ts, rec);
+      return launch_step_t<float, double>(h, h->kd, mode, st, src, dst, mac, init_tf, init_ts, rec, stream);
     default:
-      return launch_step_t<_Float16, float>(h, h->kf, mode, st, src, dst, mac, init_tf, init_ts, rec);
+      return launch_step_t<_Float16, float>(h, h->kf, mode, st, src, dst, mac, init_tf, init_ts, rec, stream);
   }
 }
 
@@ -555,33 +558,61 @@ int adjoint_t(lbm_ltne* h, int64_t nsteps, int64_t K, double* loss, double* dphi
   const size_t lamb = align_up(static_cast<size_t>(kPlanes) * ag.lplane * sizeof(Lm), kAlign);
   const size_t gb = align_up(n * sizeof(double), kAlign);
   const size_t fb = align_up(n * sizeof(R), kAlign);
-  const size_t total = nseg * popb + 2 * popb + recb + 2 * lamb + 2 * gb + 3 * fb;
+  auto total_for = [&](int nbuf) { return nseg * popb + 2 * popb + nbuf * recb + 2 * lamb + 2 * gb + 3 * fb; };
 
-  // Work memory, released on every path out (after the stream drained).
+  // Work memory, a second stream and its events, released on every path out
+  // (after both streams drained).
   struct Work {
     char* buf = nullptr;
-    hipStream_t main = nullptr;
+    hipStream_t main = nullptr, side = nullptr;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     ~Work() {
+      if (side) (void)hipStreamSynchronize(side);
       if (main) (void)hipStreamSynchronize(main);
+      for (hipEvent_t& x : ev)
+        if (x) (void)hipEventDestroy(x);
+      if (side) (void)hipStreamDestroy(side);
       if (buf) (void)hipFree(buf);
     }
   } wk;
   wk.main = h->stream;
-  if (hipMalloc(&wk.buf, total) != hipSuccess) {
+  // Segments are recomputed on the second stream into one of two recording
+  // buffers while the main stream sweeps the segment after them backwards
+  // from the other, so the two latency-bound kernels share the machine; with
+  // memory for one buffer only, recompute and sweep alternate.
+  int nbuf = 2;
+  if (hipMalloc(&wk.buf, total_for(2)) != hipSuccess) {
     wk.buf = nullptr;
     (void)hipGetLastError();
-    return set_error(LBM_ENOMEM, "adjoint work memory of %zu bytes failed", total);
+    nbuf = 1;
+    if (hipMalloc(&wk.buf, total_for(1)) != hipSuccess) {
+      wk.buf = nullptr;
+      (void)hipGetLastError();
+      return set_error(LBM_ENOMEM, "adjoint work memory of %zu bytes failed", total_for(1));
+    }
   }
   hipError_t e;
   auto hip_fail = [&](hipError_t err, const char* what) {
     return set_error(LBM_EHIP, "adjoint %s: %s", what, hipGetErrorString(err));
   };
+  if ((e = hipStreamCreateWithFlags(&wk.side, hipStreamNonBlocking)) != hipSuccess) {
+    wk.side = nullptr;
+    return hip_fail(e, "stream");
+  }
+  for (hipEvent_t& x : wk.ev)
+    if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming)) != hipSuccess) {
+      x = nullptr;
+      return hip_fail(e, "event");
+    }
+  hipEvent_t ev_fwd = wk.ev[0];
+  hipEvent_t ev_rec[2] = {wk.ev[1], wk.ev[2]};    // segment recorded into buffer i
+  hipEvent_t ev_sweep[2] = {wk.ev[3], wk.ev[4]};  // sweep done reading buffer i
 
   char* ckpt = wk.buf;
   char* work[2] = {ckpt + nseg * popb, ckpt + nseg * popb + popb};
-  R* rec = reinterpret_cast<R*>(work[1] + popb);
-  Lm* lam[2] = {reinterpret_cast<Lm*>(reinterpret_cast<char*>(rec) + recb),
-                reinterpret_cast<Lm*>(reinterpret_cast<char*>(rec) + recb + lamb)};
+  R* rec[2] = {reinterpret_cast<R*>(work[1] + popb), reinterpret_cast<R*>(work[1] + popb + (nbuf - 1) * recb)};
+  Lm* lam[2] = {reinterpret_cast<Lm*>(reinterpret_cast<char*>(rec[0]) + nbuf * recb),
+                reinterpret_cast<Lm*>(reinterpret_cast<char*>(rec[0]) + nbuf * recb + lamb)};
   double* gphi = reinterpret_cast<double*>(reinterpret_cast<char*>(lam[1]) + lamb);
   double* ghv = reinterpret_cast<double*>(reinterpret_cast<char*>(gphi) + gb);
   R* wseed = reinterpret_cast<R*>(reinterpret_cast<char*>(ghv) + gb);
@@ -592,6 +623,7 @@ int adjoint_t(lbm_ltne* h, int64_t nsteps, int64_t K, double* loss, double* dphi
   // A failure after this point puts the state of t0 (checkpoint 0) back.
   const int cur0 = h->cur;
   auto bail = [&](int code) {
+    (void)hipStreamSynchronize(wk.side);
     (void)hipStreamSynchronize(h->stream);
     if (hipMemcpyAsync(h->pop(cur0), ckpt, popb, hipMemcpyDeviceToDevice, h->stream) == hipSuccess)
       (void)hipStreamSynchronize(h->stream);
@@ -621,32 +653,44 @@ int adjoint_t(lbm_ltne* h, int64_t nsteps, int64_t K, double* loss, double* dphi
     return hipGetLastError();
   };
   int la = 0;
+  // the recomputes read the checkpoints of the forward
+  if ((e = hipEventRecord(ev_fwd, h->stream)) != hipSuccess) return bail(hip_fail(e, "event record"));
+  if ((e = hipStreamWaitEvent(wk.side, ev_fwd, 0)) != hipSuccess) return bail(hip_fail(e, "event wait"));
   for (int64_t sg = nseg - 1; sg >= 0; --sg) {
-    // recompute the segment, recording q of every step
-    e = hipMemcpyAsync(work[0], ckpt + sg * popb, popb, hipMemcpyDeviceToDevice, h->stream);
+    const int b = static_cast<int>(sg % nbuf);
+    R* rb = rec[b];
+    // recompute the segment on the side stream, recording q of every step,
+    // once the sweep that last read this buffer (segment sg + nbuf) is done
+    if (sg + nbuf <= nseg - 1 && (e = hipStreamWaitEvent(wk.side, ev_sweep[b], 0)) != hipSuccess)
+      return bail(hip_fail(e, "event wait"));
+    e = hipMemcpyAsync(work[0], ckpt + sg * popb, popb, hipMemcpyDeviceToDevice, wk.side);
     if (e != hipSuccess) return bail(hip_fail(e, "restore"));
     const int64_t steps_in = std::min<int64_t>(K, nsteps - sg * K);
     int wc = 0;
     for (int64_t j = 1; j <= steps_in; ++j) {
       const bool last = (sg == nseg - 1 && j == steps_in);
       e = launch_step(h, last ? 4 : 3, t0 + sg * K + j, work[wc], work[1 - wc],
-                      last ? h->mac(1 - h->mcur) : nullptr, nullptr, nullptr, rec + (j - 1) * 5 * n);
+                      last ? h->mac(1 - h->mcur) : nullptr, nullptr, nullptr, rb + (j - 1) * 5 * n, wk.side);
       if (e != hipSuccess) return bail(hip_fail(e, "recompute launch"));
       wc = 1 - wc;
     }
+    if ((e = hipEventRecord(ev_rec[b], wk.side)) != hipSuccess) return bail(hip_fail(e, "event record"));
+    // sweep it backwards on the main stream
+    if ((e = hipStreamWaitEvent(h->stream, ev_rec[b], 0)) != hipSuccess) return bail(hip_fail(e, "event wait"));
     int64_t jhi = steps_in;
     if (sg == nseg - 1) {
-      e = sweep(adjoint_kernel<Lm, C, R, kAdjSeed>, nullptr, lam[la], rec + (steps_in - 1) * 5 * n, wseed,
+      e = sweep(adjoint_kernel<Lm, C, R, kAdjSeed>, nullptr, lam[la], rb + (steps_in - 1) * 5 * n, wseed,
                 nullptr, nullptr);
       if (e != hipSuccess) return bail(hip_fail(e, "seed launch"));
       jhi = steps_in - 1;
     }
     for (int64_t j = jhi; j >= 1; --j) {
-      e = sweep(adjoint_kernel<Lm, C, R, kAdjStep>, lam[la], lam[1 - la], rec + (j - 1) * 5 * n, nullptr, nullptr,
+      e = sweep(adjoint_kernel<Lm, C, R, kAdjStep>, lam[la], lam[1 - la], rb + (j - 1) * 5 * n, nullptr, nullptr,
                 nullptr);
       if (e != hipSuccess) return bail(hip_fail(e, "adjoint launch"));
       la = 1 - la;
     }
+    if ((e = hipEventRecord(ev_sweep[b], h->stream)) != hipSuccess) return bail(hip_fail(e, "event record"));
   }
   if (include_init) {
     const R* tf = nullptr;
