@@ -228,7 +228,7 @@ int lbm_ltne_load(lbm_ltne_t h, const void *host_buf, size_t bytes);
  * with 20 x ckpt_every bytes per node when two do not fit, and then the
  * recompute and the sweep alternate) is allocated for the call.  FP64, FP32 and FP32SR forms
  * (LBM_EUNSUPPORTED for FP16 storage, and for a lattice with the correlation
- * of Eq. 52 or the correction term of Sec. 3.2).  Synchronizes.  On an error the
+ * of Eq. 52; the correction term of Sec. 3.2 is covered).  Synchronizes.  On an error the
  * lattice is left at its state on entry (unless the device itself failed).
  */
 int lbm_ltne_adjoint(lbm_ltne_t h, int64_t nsteps, int64_t ckpt_every, double *loss, double *dL_dphi,

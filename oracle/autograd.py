@@ -18,7 +18,8 @@ The step, as in the oracle:
      neighbour (diagonal at a corner) and given the prescribed values
      rho_b = rho(x_f), u_b = 0, T_b, F_b = phi_b G(T_fb);
   4. collisions in moment space: D2Q9 with the forcing M S (Eqs. 10, 12, 15,
-     17), D2Q5 for both phases with the sources (Eqs. 29-33, 37-40).
+     17), D2Q5 for both phases with the sources (Eqs. 29-33, 37-40), and the
+     correction term of Sec. 3.2 in the fluid phase when it is switched on.
 The initial state is f = w rho0, g = g^eq(T_init, 0) - w~ Sr(T_init)/2 taken as
 the pre-collision populations of t = 0, followed by the walls and collision
 of t = 0.  The loss is the mean Nusselt number of T_f over the chosen wall:
@@ -66,9 +67,8 @@ class DiffLattice:
     """One lattice in binary64 torch tensors; phi and Hv may require grad."""
 
     def __init__(self, p: dict, phi, Hv, Tf0=None, Ts0=None):
-        if int(p.get("thermal_correction", 0)) or float(p.get("pore_size", 0.0)) > 0.0:
-            raise NotImplementedError("the transcription covers the model without the "
-                                      "correction term and without the h_v correlation")
+        if float(p.get("pore_size", 0.0)) > 0.0:
+            raise NotImplementedError("the transcription covers the model without the h_v correlation")
         self.p = dict(p)
         self.d = derive(p)
         self.nx, self.ny = int(p["nx"]), int(p["ny"])
@@ -239,7 +239,14 @@ class DiffLattice:
                  (1.0, d["eta_a"], d["eta_a"], p["eta_e"], p["eta_nu"]))):
             q = torch.tensor(rates, dtype=DT).view(5, 1, 1)
             n, neq, psi = mv(self.N, g), mv(self.N, geq), mv(self.N, wt * Sr)
-            out.append(mv(self.Ni, n - q * (n - neq) + (1.0 - 0.5 * q) * psi))
+            ns = n - q * (n - neq) + (1.0 - 0.5 * q) * psi
+            if g is gf and int(p.get("thermal_correction", 0)):
+                # correction term of Sec. 3.2: C~_i = w~_i T_f (e_i . F) / (phi cs_T^2)
+                ex = torch.tensor(EX[:5], dtype=DT).view(5, 1, 1)
+                ey = torch.tensor(EY[:5], dtype=DT).view(5, 1, 1)
+                ct = wt * m["Tf"] * (ex * m["Fx"] + ey * m["Fy"]) / (phi * d["csT2"])
+                ns = ns + (1.0 - 0.5 * q) * mv(self.N, ct)
+            out.append(mv(self.Ni, ns))
         return tuple(out)
 
     def _stream(self, a, k):

@@ -202,6 +202,18 @@ __device__ __forceinline__ void adj_interior(const NodeMacros<C>& m, const MomAd
   b.jy -= k.s_q * L.f[6];
   b.advx += k.z_a * (L.a[1] - L.s[1]);
   b.advy += k.z_a * (L.a[2] - L.s[2]);
+  // correction term of Sec. 3.2: tc T_f (rho F) / (phi rho) on the fluid heat
+  // flux, minus that on the difference lattice (tc = 0 when it is off)
+  {
+    const C cxa = k.tc * (L.a[1] - L.s[1]), cya = k.tc * (L.a[2] - L.s[2]);
+    const C w = m.Tf * m.ip * m.ir;
+    const C cf = cxa * m.rFx + cya * m.rFy;
+    b.rFx += cxa * w;
+    b.rFy += cya * w;
+    b.thf += cf * m.ip * m.ir;
+    b.ip += cf * m.Tf * m.ir;
+    b.rho -= cf * w * m.ir;
+  }
   b.srf += L.a[0] + c1 * cze * (L.a[3] - L.s[3]);
   b.srs += c1 * cee * L.s[3];
   b.dsr += L.s[0];
@@ -263,6 +275,10 @@ __device__ __forceinline__ void adj_wall(const NodeMacros<C>& m, const MomAdj<A>
   gpb += -bd0b * d0b * ipb + bd1b * d1b * iqb;
   ghb += C(0.5) * k.hvf * (bd0b * ipb + k.inv_sigma * bd1b * iqb);
   if (!dirichlet) {
+    // the correction term at the wall is tc T_fb (G_bx, G_y(T_fb)): phi_b and
+    // rho cancel
+    const C ctx = k.tc * (L.a[1] - L.s[1]), cty = k.tc * (L.a[2] - L.s[2]);
+    b.thf += ctx * k.Gbx + cty * (Gyb + (thfb + k.T_ref) * k.gbeta);
     b.thf += L.a[0] + c1 * k.z_e * L.a[3] + cy * m.rho * phb * k.gbeta;
     b.D += L.s[0] + c1 * k.e_e * L.s[3] + C(2) * d0b * bsrf - C(2) * d1b * bsrs -
            C(2) * (d0b + d1b) * bdsr;

@@ -735,9 +735,8 @@ extern "C" int lbm_ltne_adjoint(lbm_ltne_t h, int64_t nsteps, int64_t ckpt_every
   if (ckpt_every > nsteps) ckpt_every = nsteps;
   if (h->p.precision == LBM_FP16S)
     return set_error(LBM_EUNSUPPORTED, "the adjoint is built for the FP64, FP32 and FP32SR forms");
-  if (h->p.pore_size > 0.0 || h->p.thermal_correction)
-    return set_error(LBM_EUNSUPPORTED,
-                     "the adjoint covers the model without the correlation of Eq. 52 and the correction term");
+  if (h->p.pore_size > 0.0)
+    return set_error(LBM_EUNSUPPORTED, "the adjoint covers the model without the correlation of Eq. 52");
   if (h->p.precision == LBM_FP64)
     return adjoint_t<double, double, double>(h, nsteps, ckpt_every, loss, dL_dphi, dL_dHv);
   if (h->p.precision == LBM_FP32SR)

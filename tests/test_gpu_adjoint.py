@@ -51,6 +51,12 @@ def _small(kind, precision=I.FP64):
                        T_wall=(0, 0, 1.0, 0), T0=0.0, Ra=2e4, Da=1e-2, phi=0.55, F_phi=0.1, Hv=40.0,
                        gamma_sf=2.0, sigma=1.2)
         extra = {}
+    elif kind == "correction":  # correction term of Sec. 3.2; adiabatic top wall, Dirichlet bottom
+        nx, ny = 37, 26
+        p = I.cavity_small(nx=nx, ny=ny, precision=precision, Ra=3e4, Da=3e-3, Hv=40.0, gamma_sf=3.0,
+                           wall_thermal=(0, 0, 0, 1), T_wall=(1.0, 0.0, 0.3, 0.0), body_force=(2e-5, 0.0),
+                           thermal_correction=1)
+        extra = {}
     else:  # initial temperature fields, cold-wall Nusselt number, adiabatic left wall,
         # unequal fluid / solid relaxation rates
         nx, ny = 33, 30
@@ -63,7 +69,7 @@ def _small(kind, precision=I.FP64):
     return p, phi, Hv, extra
 
 
-@pytest.mark.parametrize("kind", ["cavity", "periodic", "init"])
+@pytest.mark.parametrize("kind", ["cavity", "periodic", "init", "correction"])
 def test_fp64_adjoint_equals_autograd(B, kind):
     from oracle import autograd as AG
     import oracle as O

@@ -111,10 +111,11 @@ def test_batch_equals_single_with_extensions(B):
     say("batch with extensions bitwise equal to single runs")
 
 
-def test_adjoint_refuses_extensions(B):
-    for kw in (dict(thermal_correction=1), dict(pore_size=0.0135)):
-        lat = B.Lattice(I.cavity_small(nx=24, ny=20, **kw))
-        with pytest.raises(B.LtneError) as e:
-            lat.adjoint(10, 5)
-        assert e.value.code == B.LBM_EUNSUPPORTED
-        lat.step(3)  # the lattice is still usable
+def test_adjoint_refuses_the_correlation(B):
+    """The correlation's derivative is unbounded at rest; the adjoint refuses
+    it (the correction term is covered, tests/test_gpu_adjoint.py)."""
+    lat = B.Lattice(I.cavity_small(nx=24, ny=20, pore_size=0.0135))
+    with pytest.raises(B.LtneError) as e:
+        lat.adjoint(10, 5)
+    assert e.value.code == B.LBM_EUNSUPPORTED
+    lat.step(3)  # the lattice is still usable

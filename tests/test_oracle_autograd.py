@@ -28,6 +28,9 @@ def _case(kind, seed=1):
         p = I.complete(**base, wall_thermal=(0, 0, 1, 1), T_wall=(1.0, 0, 0, 0), F_phi=-1.0, nu_wall=1)
         Tf0 = 0.4 + 0.3 * r.uniform(size=(ny, nx))
         Ts0 = 0.4 + 0.3 * r.uniform(size=(ny, nx))
+    elif kind == "correction":  # correction term of Sec. 3.2, adiabatic walls included
+        p = I.complete(**base, wall_thermal=(1, 0, 0, 1), T_wall=(0, 0, 1.0, 0), F_phi=-1.0,
+                       thermal_correction=1)
     else:                     # adiabatic left wall next to the Dirichlet loss wall
         p = I.complete(**base, wall_thermal=(1, 0, 0, 1), T_wall=(0, 0, 1.0, 0), F_phi=-1.0)
     return p, phi, Hv, Tf0, Ts0
@@ -37,7 +40,7 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-@pytest.mark.parametrize("kind", ["cavity", "periodic", "init", "adiabatic"])
+@pytest.mark.parametrize("kind", ["cavity", "periodic", "init", "adiabatic", "correction"])
 def test_forward_equals_c_oracle(kind):
     p, phi, Hv, Tf0, Ts0 = _case(kind)
     for steps in (0, 1, 30):
@@ -67,7 +70,7 @@ def _fd(p, field, phi, Hv, cell, h, Tf0=None, Ts0=None, t0=0, pops=None, steps=2
 CELLS = [(5, 6), (1, 1), (0, 0), (0, 5), (5, 0), (9, 11), (2, 2), (8, 3), (1, 10), (9, 4)]
 
 
-@pytest.mark.parametrize("kind", ["cavity", "periodic", "init", "adiabatic"])
+@pytest.mark.parametrize("kind", ["cavity", "periodic", "init", "adiabatic", "correction"])
 def test_gradients_equal_central_differences(kind):
     """Central differences with a relative step of 3e-4 have a truncation
     error near 1e-8 of the gradient scale and a rounding error below that."""
