@@ -93,9 +93,6 @@ int derive(const lbm_ltne_params* p, double tmin, double tmax, lbm_ltne_derived*
                      p->nx, p->ny);
   if (static_cast<long long>(p->nx) * p->ny > (1LL << 30))
     return set_error(LBM_EINVAL, "lattice %d x %d exceeds 2^30 nodes", p->nx, p->ny);
-  if (p->precision == LBM_FP64 && static_cast<long long>(p->nx) * p->ny * 8 >= (1LL << 32))
-    return set_error(LBM_EINVAL, "FP64 lattice %d x %d: a population plane must stay below 4 GiB",
-                     p->nx, p->ny);
   for (int w = 0; w < 4; ++w)
     if (walled(p, w) && p->wall_thermal[w] != LBM_WALL_DIRICHLET &&
         p->wall_thermal[w] != LBM_WALL_ADIABATIC)

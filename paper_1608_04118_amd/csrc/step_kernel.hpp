@@ -30,9 +30,9 @@ __device__ __forceinline__ S load_raw(const S* __restrict__ p) {
   }
 }
 
-// Element i of a plane: a uniform 64-bit plane base plus a 32-bit byte
-// offset (the host keeps every plane below 4 GiB), which maps to the
-// scalar-base + vector-offset form of the global memory instructions.
+// Element i of a population row: a wave-uniform 64-bit row base plus the
+// lane's 32-bit byte offset, which maps to the scalar-base + vector-offset
+// form of the global memory instructions.
 template <typename S>
 __device__ __forceinline__ const S* at(const S* __restrict__ base, uint32_t i) {
   return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + i * static_cast<uint32_t>(sizeof(S)));

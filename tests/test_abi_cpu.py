@@ -80,7 +80,7 @@ BAD = [
     dict(precision=4), dict(periodic_x=2), dict(Ma=0.0, nu_f=0.0), dict(Ra=0.0, nu_f=0.0),
     dict(gamma_sf=0.0), dict(Hv=-1.0), dict(sigma=0.0), dict(Je=0.0), dict(rho0=0.0),
     dict(nu_wall=5), dict(wall_thermal=(0, 0, 2, 1)), dict(fp16_scale_f=3.0),
-    dict(Ra=float("nan")), dict(nx=40000, ny=40000), dict(nx=23171, ny=23171),
+    dict(Ra=float("nan")), dict(nx=40000, ny=40000), dict(nx=32769, ny=32768),
     dict(thermal_correction=2), dict(pore_size=-0.01), dict(pore_size=float("inf")),
 ]
 
@@ -97,6 +97,7 @@ def test_validation_rejects(lib, bad):
 
 def test_validation_accepts_edges(lib):
     B.lbm_ltne_derive(I.cavity_small(nx=23171, ny=23171, precision=I.FP32))
+    B.lbm_ltne_derive(I.cavity_small(nx=32768, ny=32768))  # 2^30 nodes, the limit, in every form
     B.lbm_ltne_derive(I.cavity_small(nx=4, ny=4))
     B.lbm_ltne_derive(I.complete(nx=3, ny=3, periodic_x=1, periodic_y=1, nu_f=0.1, Ma=0.0))
     B.lbm_ltne_derive(I.cavity_small(Hv=0.0, fp16_scale_f=1024.0, precision=I.FP16S))

@@ -60,3 +60,16 @@ def test_maximum_lattice_fp32(B, oracle):
     say("strips at x = 0, n/2, n - 16 after %d steps:" % steps, {k: "%.2e" % v for k, v in worst.items()})
     for k, v in worst.items():
         assert v <= 1e-5, (k, v)
+
+
+def test_lattice_beyond_device_memory_is_refused(B):
+    """2^30 nodes in binary64 need 2 x 163 GB of populations, more than the
+    device holds: creation fails with LBM_ENOMEM and leaves nothing behind."""
+    n = 32768
+    p = I.complete(nx=n, ny=n, precision=I.FP64, periodic_x=1, nu_f=0.1, Ma=0.0, Ra=1e5)
+    with pytest.raises(B.LtneError) as e:
+        B.Lattice(p, use_torch=False)
+    assert e.value.code == B.LBM_ENOMEM
+    say("binary64 2^30 nodes refused:", B.lbm_ltne_last_error())
+    lat = B.Lattice(I.cavity_small(nx=40, ny=30), use_torch=False).step(5)  # the device is still usable
+    assert np.isfinite(lat.macros()["Tf"]).all()
