@@ -14,6 +14,7 @@
 #include "reduce_kernels.hpp"
 #include "adjoint_kernel.hpp"
 #include "step_kernel.hpp"
+#include "step2_kernel.hpp"
 
 using namespace ltne;
 
@@ -127,6 +128,54 @@ hipError_t launch_step(const lbm_ltne* h, int mode, int64_t step, const void* sr
     default:
       return launch_step_t<_Float16, float>(h, h->kf, mode, st, src, dst, mac, init_tf, init_ts, rec, stream);
   }
+}
+
+#ifndef LTNE_STEP2_ROWS
+#define LTNE_STEP2_ROWS 8
+#endif
+#ifndef LTNE_STEP2_MIN_WAVES
+#define LTNE_STEP2_MIN_WAVES 1024
+#endif
+
+// Geometry of the two-step kernel: strips of 64 lanes (63 - halo output
+// columns), chunks of LTNE_STEP2_ROWS rows, four wavefronts per workgroup,
+// workgroups dealt to the XCDs in contiguous ranges.
+Step2Map step2_map(const lbm_ltne_params& p) {
+  Step2Map m{};
+  m.halo = p.periodic_x ? 1 : 2;
+  m.out = 63 - m.halo;
+  m.nstrips = (p.nx + m.out - 1) / m.out;
+  m.rows = LTNE_STEP2_ROWS;
+  m.nchunks = (p.ny + m.rows - 1) / m.rows;
+  m.nwaves = m.nstrips * m.nchunks;
+  const int nblocks = (m.nwaves + kBlock / 64 - 1) / (kBlock / 64);
+  m.per_xcd = (nblocks + kXcds - 1) / kXcds;
+  return m;
+}
+
+// Two steps of the FP32 form in one launch (no macro output).
+hipError_t launch_step2(const lbm_ltne* h, int64_t step, const void* src, void* dst) {
+  const Step2Map m = step2_map(h->p);
+  const dim3 grid(kXcds * m.per_xcd), block(kBlock);
+  const uint32_t st = static_cast<uint32_t>(step);
+  const float* s = static_cast<const float*>(src);
+  float* d = static_cast<float*>(dst);
+  const float* phi = static_cast<const float*>(h->phi());
+  const float* hv = static_cast<const float*>(h->hv());
+  const int fl = (h->has_phi ? kPhiField : 0) | (h->has_hv ? kHvField : 0);
+  switch (fl) {
+    case 0: hipLaunchKernelGGL(step2_kernel<0>, grid, block, 0, h->stream, s, d, phi, hv, h->kf, m, st); break;
+    case kPhiField:
+      hipLaunchKernelGGL(step2_kernel<kPhiField>, grid, block, 0, h->stream, s, d, phi, hv, h->kf, m, st);
+      break;
+    case kHvField:
+      hipLaunchKernelGGL(step2_kernel<kHvField>, grid, block, 0, h->stream, s, d, phi, hv, h->kf, m, st);
+      break;
+    default:
+      hipLaunchKernelGGL(step2_kernel<kPhiField | kHvField>, grid, block, 0, h->stream, s, d, phi, hv, h->kf, m,
+                         st);
+  }
+  return hipGetLastError();
 }
 
 // Copies a host double field to device memory in the compute type.
@@ -284,7 +333,21 @@ int lbm_ltne_step(lbm_ltne_t h, int64_t nsteps) {
   if (!h) return set_error(LBM_EINVAL, "handle is NULL");
   if (nsteps < 0) return set_error(LBM_EINVAL, "nsteps = %lld < 0", static_cast<long long>(nsteps));
   if (nsteps == 0) return LBM_OK;
-  for (int64_t s = 0; s < nsteps; ++s) {
+  int64_t s = 0;
+  // two steps per launch where the lattice gives the two-step kernel enough
+  // wavefronts to hide its latency (each wavefront runs a serial chain of
+  // rows); small lattices run faster one step at a time
+  if (h->p.precision == LBM_FP32 && step2_map(h->p).nwaves >= LTNE_STEP2_MIN_WAVES) {
+    // pairs of steps in one launch while more than the last step (which
+    // also writes the macros) remain
+    for (; s + 2 <= nsteps - 1; s += 2) {
+      hipError_t e = launch_step2(h, h->steps + 1, h->pop(h->cur), h->pop(1 - h->cur));
+      if (e != hipSuccess) return set_error(LBM_EHIP, "step launch: %s", hipGetErrorString(e));
+      h->cur = 1 - h->cur;
+      h->steps += 2;
+    }
+  }
+  for (; s < nsteps; ++s) {
     const bool last = (s == nsteps - 1);
     hipError_t e = launch_step(h, last ? 1 : 0, h->steps + 1, h->pop(h->cur), h->pop(1 - h->cur),
                                last ? h->mac(1 - h->mcur) : nullptr, nullptr, nullptr);

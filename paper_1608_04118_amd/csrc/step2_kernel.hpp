@@ -1,0 +1,170 @@
+// Two fused time steps per launch for the FP32 form (binary32 storage and
+// arithmetic).  The single-step kernel is bound by memory traffic at about
+// 450 vector instructions per 156 bytes; computing two steps per pass over
+// the populations halves the traffic per lattice-node update.
+//
+// Each wavefront owns a strip of columns and a chunk of rows and marches
+// down the rows.  Lane l holds column x0 - H + l (H = 1 on a periodic x axis,
+// 2 with x walls, whose nodes pull from two columns inward).  At row y it
+//   1. updates its column at row y + 1 to time t + 1 from device memory (the
+//      ordinary pull and node update), keeping the 19 results in registers:
+//      a window of three rows, y - 1, y, y + 1;
+//   2. gathers the pulls of its node at row y from the window, the column
+//      offsets by cross-lane permutes;
+//   3. updates the node at row y to time t + 2 and stores it.
+// The lanes at the strip edges only feed their neighbours.  A wall row takes
+// the pulls of its inward neighbour row (non-equilibrium extrapolation), so
+// it is updated at that row's step.  The results equal two single steps bit
+// for bit: the same node update, and binary32 values in registers instead of
+// a binary32 round trip through memory.
+#pragma once
+
+#include "step_kernel.hpp"
+
+namespace ltne {
+
+// Launch geometry of the two-step kernel.
+struct Step2Map {
+  int halo;     // lanes left of the first output column (1 or 2)
+  int out;      // output columns per strip (63 - halo)
+  int nstrips;  // strips across the lattice
+  int rows;     // rows per chunk
+  int nchunks;  // chunks down the lattice
+  int nwaves;   // nstrips * nchunks
+  int per_xcd;  // workgroups per XCD
+};
+
+// Put into registers: the 19 post-collision populations of one node.
+template <typename C>
+struct RegPut {
+  C* v;
+  __device__ __forceinline__ void begin(int, int, const StepConsts<C>&) {}
+  __device__ __forceinline__ void pair(int i, C va, C, int j, C vb, C, uint32_t, half2_t&) {
+    v[i] = va;
+    v[j] = vb;
+  }
+  __device__ __forceinline__ void single(int i, C val, C, uint32_t) { v[i] = val; }
+};
+
+// Pull from registers: populations already gathered for the node.
+template <typename C>
+struct RegPull {
+  const C* g;
+  __device__ __forceinline__ void operator()(int, int, const StepConsts<C>&, C (&v)[kPlanes]) const {
+#pragma unroll
+    for (int i = 0; i < kPlanes; ++i) v[i] = g[i];
+  }
+};
+
+template <int F>
+__global__ __launch_bounds__(kBlock) void step2_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                                                       const float* __restrict__ phi_field,
+                                                       const float* __restrict__ hv_field,
+                                                       const StepConsts<float> k, const Step2Map m,
+                                                       const uint32_t step) {
+  const int b = blockIdx.x;
+  const int blk = (b & (kXcds - 1)) * m.per_xcd + (b >> 3);
+  const int wave = blk * (kBlock / 64) + (static_cast<int>(threadIdx.x) >> 6);
+  if (wave >= m.nwaves) return;  // whole wavefronts
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  const int nx = k.nx, ny = k.ny;
+  const int strip = wave % m.nstrips, chunk = wave / m.nstrips;
+  const int x0 = strip * m.out;
+  // column of this lane at time t + 1
+  int col = x0 - m.halo + lane;
+  bool colok = true;
+  if (k.px) {
+    col %= nx;
+    if (col < 0) col += nx;
+  } else {
+    colok = col >= 0 && col < nx;
+  }
+  // output column and the column offset of its pulls (x walls pull inward)
+  const int xo = x0 - m.halo + lane;
+  const bool outlane = lane >= m.halo && lane < m.halo + m.out && xo < nx;
+  const int dx = (!k.px && xo == 0) ? 1 : ((!k.px && xo == nx - 1) ? -1 : 0);
+  // rows of this chunk; a wall row is updated with its inward neighbour row
+  int y_lo = chunk * m.rows, y_hi = y_lo + m.rows < ny ? y_lo + m.rows : ny;
+  if (!k.py) {
+    y_lo = y_lo > 1 ? y_lo : 1;
+    y_hi = y_hi < ny - 1 ? y_hi : ny - 1;
+  }
+  if (y_lo >= y_hi) return;
+
+  const GlobalPull<float, float> gpull{src};
+  // row r at this lane's column, wrapped on a periodic axis; ok: a node exists
+  auto row_of = [&](int r, bool& ok) {
+    ok = colok;
+    if (k.py) return r < 0 ? r + ny : (r >= ny ? r - ny : r);
+    ok = ok && r >= 0 && r < ny;
+    return r;
+  };
+  // the pulls of node (col, r) at time t (a wall node pulls those of its
+  // inward neighbour), issued one row ahead of their use so the loads
+  // overlap the arithmetic of the row before
+  auto fetch = [&](int r, float (&v)[kPlanes]) {
+    bool ok;
+    r = row_of(r, ok);
+    if (ok) {
+      const int xc = (!k.px && col == 0) ? 1 : ((!k.px && col == nx - 1) ? nx - 2 : col);
+      const int yc = (!k.py && r == 0) ? 1 : ((!k.py && r == ny - 1) ? ny - 2 : r);
+      gpull(xc, yc, k, v);
+    }
+  };
+  // node (col, r) at time t + 1 from its fetched pulls into w; zeros where
+  // there is no node
+  auto advance = [&](int r, const float (&v)[kPlanes], float (&w)[kPlanes]) {
+    bool ok;
+    r = row_of(r, ok);
+    if (ok) {
+      const RegPull<float> rp{v};
+      RegPut<float> put{w};
+      node_update_with<float, float, F>(col, r, rp, put, phi_field, hv_field, nullptr, nullptr, nullptr, k, step,
+                                        nullptr);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kPlanes; ++i) w[i] = 0.0f;
+    }
+  };
+
+  float wa[kPlanes], wb[kPlanes], wc[kPlanes];  // time t + 1 at rows y - 1, y, y + 1
+  float pa[kPlanes], pb[kPlanes];               // fetched pulls of two rows
+  fetch(y_lo - 1, pa);
+  fetch(y_lo, pb);
+  advance(y_lo - 1, pa, wa);
+  fetch(y_lo + 1, pa);
+  advance(y_lo, pb, wb);
+  for (int y = y_lo; y < y_hi; ++y) {
+    advance(y + 1, pa, wc);
+    if (y + 1 < y_hi) fetch(y + 2, pa);
+    // pulls of node (xo + dx, y) at time t + 1: population i from column
+    // xo + dx - e_ix (lane offset) and row y - e_iy (window row)
+    float g[kPlanes];
+#pragma unroll
+    for (int i = 0; i < kPlanes; ++i) {
+      const int q = i < 9 ? i : (i < 14 ? i - 9 : i - 14);
+      const float v = vel_y(q) == 1 ? wa[i] : (vel_y(q) == -1 ? wc[i] : wb[i]);
+      const int sl = (lane + dx - vel_x(q)) & 63;
+      g[i] = __shfl(v, sl, 64);
+    }
+    if (outlane) {
+      const RegPull<float> rpull{g};
+      GlobalPut<float, float> put{dst};
+      node_update_with<float, float, F>(xo, y, rpull, put, phi_field, hv_field, nullptr, nullptr, nullptr, k,
+                                        step + 1u, nullptr);
+      if (!k.py && y == 1)
+        node_update_with<float, float, F>(xo, 0, rpull, put, phi_field, hv_field, nullptr, nullptr, nullptr, k,
+                                          step + 1u, nullptr);
+      if (!k.py && y == ny - 2)
+        node_update_with<float, float, F>(xo, ny - 1, rpull, put, phi_field, hv_field, nullptr, nullptr, nullptr,
+                                          k, step + 1u, nullptr);
+    }
+#pragma unroll
+    for (int i = 0; i < kPlanes; ++i) {
+      wa[i] = wb[i];
+      wb[i] = wc[i];
+    }
+  }
+}
+
+}  // namespace ltne

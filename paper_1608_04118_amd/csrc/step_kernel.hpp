@@ -160,6 +160,83 @@ __device__ __forceinline__ C pow_0644(C v) {
   }
 }
 
+// Where a node update takes its 19 pulled populations from and puts its 19
+// post-collision ones.  The global forms read and write the population
+// buffers in device memory; the two-step kernel substitutes register and
+// cross-lane forms for its intermediate time level.
+
+// Pull: population i arrives from node (xc, yc) - e_i.  A wave covers part
+// of one lattice row, so the three source rows are wave-uniform: their bases
+// are formed once in scalar registers (readfirstlane tells the compiler) and
+// every load is a scalar base plus the lane's x.
+template <typename S, typename C>
+struct GlobalPull {
+  const S* __restrict__ src;
+  __device__ __forceinline__ void operator()(int xc, int yc, const StepConsts<C>& k, C (&v)[kPlanes]) const {
+    const int nx = k.nx, ny = k.ny;
+    const int yu = __builtin_amdgcn_readfirstlane(yc);
+    int xm = xc - 1, xp = xc + 1, ym = yu - 1, yp = yu + 1;
+    if (k.px) {
+      xm = (xc == 0) ? nx - 1 : xm;
+      xp = (xc == nx - 1) ? 0 : xp;
+    }
+    if (k.py) {
+      ym = (yu == 0) ? ny - 1 : ym;
+      yp = (yu == ny - 1) ? 0 : yp;
+    }
+    const long long Q = k.qs;
+    const S* __restrict__ s0 = src + yu * k.rs;
+    const S* __restrict__ sm = src + ym * k.rs;
+    const S* __restrict__ sp = src + yp * k.rs;
+    const C isf = k.inv_sf, isg = k.inv_sg;
+    v[0] = load_pop(at(s0 + 0 * Q, xc), isf);
+    v[1] = load_pop(at(s0 + 1 * Q, xm), isf);
+    v[2] = load_pop(at(sm + 2 * Q, xc), isf);
+    v[3] = load_pop(at(s0 + 3 * Q, xp), isf);
+    v[4] = load_pop(at(sp + 4 * Q, xc), isf);
+    v[5] = load_pop(at(sm + 5 * Q, xm), isf);
+    v[6] = load_pop(at(sm + 6 * Q, xp), isf);
+    v[7] = load_pop(at(sp + 7 * Q, xp), isf);
+    v[8] = load_pop(at(sp + 8 * Q, xm), isf);
+    v[9] = load_pop(at(s0 + 9 * Q, xc), isg);
+    v[10] = load_pop(at(s0 + 10 * Q, xm), isg);
+    v[11] = load_pop(at(sm + 11 * Q, xc), isg);
+    v[12] = load_pop(at(s0 + 12 * Q, xp), isg);
+    v[13] = load_pop(at(sp + 13 * Q, xc), isg);
+    v[14] = load_pop(at(s0 + 14 * Q, xc), isg);
+    v[15] = load_pop(at(s0 + 15 * Q, xm), isg);
+    v[16] = load_pop(at(sm + 16 * Q, xc), isg);
+    v[17] = load_pop(at(s0 + 17 * Q, xp), isg);
+    v[18] = load_pop(at(sp + 18 * Q, xc), isg);
+  }
+};
+
+// Put: the node's own 19 slots of the destination buffer, in pairs that
+// share one random word (see store_pair).
+template <typename S, typename C>
+struct GlobalPut {
+  S* __restrict__ dst;
+  S* __restrict__ drow = nullptr;
+  long long P = 0;
+  int x = 0;
+  __device__ __forceinline__ void begin(int x_, int y, const StepConsts<C>& k) {
+    drow = dst + static_cast<long long>(__builtin_amdgcn_readfirstlane(y)) * k.rs;
+    P = k.qs;
+    x = x_;
+  }
+  __device__ __forceinline__ void pair(int i, C va, C sa, int j, C vb, C sb, uint32_t w, half2_t& h) {
+    store_pair(at(drow + i * P, x), va, sa, at(drow + j * P, x), vb, sb, w, h);
+  }
+  __device__ __forceinline__ void single(int i, C v, C s, uint32_t r) { store_pop(at(drow + i * P, x), v, s, r); }
+};
+
+template <typename S, typename C, int F, class Pull, class Put>
+__device__ __forceinline__ void node_update_with(
+    const int x, const int y, const Pull& pull, Put& put,
+    const C* __restrict__ phi_field, const C* __restrict__ hv_field, C* __restrict__ mac,
+    const C* __restrict__ init_tf, const C* __restrict__ init_ts, const StepConsts<C>& k,
+    const uint32_t step, C* __restrict__ rec);
+
 // One node update: pull, macros, walls, collisions, store.  step numbers
 // the time step being computed (0: initialisation); with a narrow storage
 // form it seeds the stochastic rounding of the stores.
@@ -169,6 +246,17 @@ __device__ __forceinline__ void node_update(
     const C* __restrict__ phi_field, const C* __restrict__ hv_field, C* __restrict__ mac,
     const C* __restrict__ init_tf, const C* __restrict__ init_ts, const StepConsts<C>& k,
     const uint32_t step, C* __restrict__ rec = nullptr) {
+  const GlobalPull<S, C> pull{src};
+  GlobalPut<S, C> put{dst};
+  node_update_with<S, C, F>(x, y, pull, put, phi_field, hv_field, mac, init_tf, init_ts, k, step, rec);
+}
+
+template <typename S, typename C, int F, class Pull, class Put>
+__device__ __forceinline__ void node_update_with(
+    const int x, const int y, const Pull& pull, Put& put,
+    const C* __restrict__ phi_field, const C* __restrict__ hv_field, C* __restrict__ mac,
+    const C* __restrict__ init_tf, const C* __restrict__ init_ts, const StepConsts<C>& k,
+    const uint32_t step, C* __restrict__ rec) {
   const int nx = k.nx, ny = k.ny;
 
   // Wall classification and the node whose post-streaming populations this
@@ -205,44 +293,11 @@ __device__ __forceinline__ void node_update(
     b0 = w0 * gh;
     b1 = b2 = b3 = b4 = w1 * gh;
   } else {
-    // Pull: population i arrives from node (xc, yc) - e_i.  A wave covers
-    // part of one lattice row, so the three source rows are wave-uniform:
-    // their bases are formed once in scalar registers (readfirstlane tells
-    // the compiler) and every load is a scalar base plus the lane's x.
-    const int yu = __builtin_amdgcn_readfirstlane(yc);
-    int xm = xc - 1, xp = xc + 1, ym = yu - 1, yp = yu + 1;
-    if (k.px) {
-      xm = (xc == 0) ? nx - 1 : xm;
-      xp = (xc == nx - 1) ? 0 : xp;
-    }
-    if (k.py) {
-      ym = (yu == 0) ? ny - 1 : ym;
-      yp = (yu == ny - 1) ? 0 : yp;
-    }
-    const long long Q = k.qs;
-    const S* __restrict__ s0 = src + yu * k.rs;
-    const S* __restrict__ sm = src + ym * k.rs;
-    const S* __restrict__ sp = src + yp * k.rs;
-    const C isf = k.inv_sf, isg = k.inv_sg;
-    f0 = load_pop(at(s0 + 0 * Q, xc), isf);
-    f1 = load_pop(at(s0 + 1 * Q, xm), isf);
-    f2 = load_pop(at(sm + 2 * Q, xc), isf);
-    f3 = load_pop(at(s0 + 3 * Q, xp), isf);
-    f4 = load_pop(at(sp + 4 * Q, xc), isf);
-    f5 = load_pop(at(sm + 5 * Q, xm), isf);
-    f6 = load_pop(at(sm + 6 * Q, xp), isf);
-    f7 = load_pop(at(sp + 7 * Q, xp), isf);
-    f8 = load_pop(at(sp + 8 * Q, xm), isf);
-    a0 = load_pop(at(s0 + 9 * Q, xc), isg);
-    a1 = load_pop(at(s0 + 10 * Q, xm), isg);
-    a2 = load_pop(at(sm + 11 * Q, xc), isg);
-    a3 = load_pop(at(s0 + 12 * Q, xp), isg);
-    a4 = load_pop(at(sp + 13 * Q, xc), isg);
-    b0 = load_pop(at(s0 + 14 * Q, xc), isg);
-    b1 = load_pop(at(s0 + 15 * Q, xm), isg);
-    b2 = load_pop(at(sm + 16 * Q, xc), isg);
-    b3 = load_pop(at(s0 + 17 * Q, xp), isg);
-    b4 = load_pop(at(sp + 18 * Q, xc), isg);
+    C v[kPlanes];
+    pull(xc, yc, k, v);
+    f0 = v[0]; f1 = v[1]; f2 = v[2]; f3 = v[3]; f4 = v[4]; f5 = v[5]; f6 = v[6]; f7 = v[7]; f8 = v[8];
+    a0 = v[9]; a1 = v[10]; a2 = v[11]; a3 = v[12]; a4 = v[13];
+    b0 = v[14]; b1 = v[15]; b2 = v[16]; b3 = v[17]; b4 = v[18];
   }
 
   // ---- macros at (xc, yc) ----
@@ -406,9 +461,8 @@ __device__ __forceinline__ void node_update(
     mac[4 * k.mplane + ib] = ths + k.T_ref;
   }
 
-  const long long P = k.qs;
   const int io = y * nx + x;  // node index (hash input)
-  S* __restrict__ drow = dst + static_cast<long long>(__builtin_amdgcn_readfirstlane(y)) * k.rs;
+  put.begin(x, y, k);
   // 19 x 16 random bits for the stores, two stores per word (its top and
   // its bottom half moved to the top); unused by the same-type forms
   uint32_t rb[10];
@@ -479,10 +533,10 @@ __device__ __forceinline__ void node_update(
     const C o4 = o2 + ((o5 + o6) - (o7 + o8)) - ms5;
     const C o0 = ms0 - (((o1 + o2) + (o3 + o4)) + ((o5 + o6) + (o7 + o8)));
     const C sf = k.sf;
-    store_pair(at(drow + 0 * P, x), o0, sf, at(drow + 1 * P, x), o1, sf, rb[0], hs);
-    store_pair(at(drow + 2 * P, x), o2, sf, at(drow + 3 * P, x), o3, sf, rb[1], hs);
-    store_pair(at(drow + 4 * P, x), o4, sf, at(drow + 5 * P, x), o5, sf, rb[2], hs);
-    store_pair(at(drow + 6 * P, x), o6, sf, at(drow + 7 * P, x), o7, sf, rb[3], hs);
+    put.pair(0, o0, sf, 1, o1, sf, rb[0], hs);
+    put.pair(2, o2, sf, 3, o3, sf, rb[1], hs);
+    put.pair(4, o4, sf, 5, o5, sf, rb[2], hs);
+    put.pair(6, o6, sf, 7, o7, sf, rb[3], hs);
     f8_out = o8;  // stored with the first thermal population, sharing its random word
   }
 
@@ -514,10 +568,10 @@ __device__ __forceinline__ void node_update(
       const C r1 = o0 + h1 + o3 + o4, r2 = o0 + h2 + o3 - o4;
       const C r3 = o0 - h1 + o3 + o4, r4 = o0 - h2 + o3 - o4;
       // rest population from the conserved zeroth moment (see the flow part)
-      store_pair(at(drow + 8 * P, x), f8_out, k.sf, at(drow + 9 * P, x), nf0 - ((r1 + r2) + (r3 + r4)), sg,
+      put.pair(8, f8_out, k.sf, 9, nf0 - ((r1 + r2) + (r3 + r4)), sg,
                  rb[4], hs);
-      store_pair(at(drow + 10 * P, x), r1, sg, at(drow + 11 * P, x), r2, sg, rb[5], hs);
-      store_pair(at(drow + 12 * P, x), r3, sg, at(drow + 13 * P, x), r4, sg, rb[6], hs);
+      put.pair(10, r1, sg, 11, r2, sg, rb[5], hs);
+      put.pair(12, r3, sg, 13, r4, sg, rb[6], hs);
     }
     // solid phase (Eq. 33, equilibria of Eq. 38), carried as the difference
     // g_s - g_f: in moments, n_h* = n_s* - n_f* with n_s = n_f + n_h,
@@ -545,10 +599,10 @@ __device__ __forceinline__ void node_update(
       const C h1 = ns1 * C(0.5), h2 = ns2 * C(0.5);
       const C r1 = o0 + h1 + o3 + o4, r2 = o0 + h2 + o3 - o4;
       const C r3 = o0 - h1 + o3 + o4, r4 = o0 - h2 + o3 - o4;
-      store_pair(at(drow + 14 * P, x), nh0 - ((r1 + r2) + (r3 + r4)), sg, at(drow + 15 * P, x), r1, sg, rb[7],
+      put.pair(14, nh0 - ((r1 + r2) + (r3 + r4)), sg, 15, r1, sg, rb[7],
                  hs);
-      store_pair(at(drow + 16 * P, x), r2, sg, at(drow + 17 * P, x), r3, sg, rb[8], hs);
-      store_pop(at(drow + 18 * P, x), r4, sg, (rb[9] << 16));
+      put.pair(16, r2, sg, 17, r3, sg, rb[8], hs);
+      put.single(18, r4, sg, (rb[9] << 16));
     }
   }
 }

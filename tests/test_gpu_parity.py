@@ -256,3 +256,36 @@ def test_step_zero_and_errors(B):
     assert g.steps == 0
     with pytest.raises(B.LtneError):
         B.lbm_ltne_step(g.h, -1)
+
+
+# Lattices large enough for two-step launches (at least 1024 wavefronts of
+# 61 or 62 columns x 8 rows), with the strip and chunk edges falling on the
+# awkward places: a wall column at the start of a strip (1038 = 17 x 61 + 1),
+# a ragged last chunk, periodic wraps on either axis.
+TWO_STEP_CASES = [
+    ("layer 1100x1027, phi field", lambda: I.throughput(n=1100, ny=1027)),
+    ("cavity 1038x1030", lambda: (I.cavity_small(nx=1038, ny=1030, precision=I.FP32, Ra=1e5), None, None, None)),
+    ("torus 1030x1030", lambda: (I.complete(nx=1030, ny=1030, periodic_x=1, periodic_y=1, precision=I.FP32,
+                                            Ra=1e4, body_force=(1e-4, -2e-5)), None, None, None)),
+    ("channel along y 1030x1040", lambda: (I.channel(nx=1030, ny=1040, axis="y"), None, None, None)),
+    ("cavity 1024x1024, both extensions", lambda: (I.cavity_small(nx=1024, ny=1024, precision=I.FP32, Ra=1e5,
+                                                                  thermal_correction=1, pore_size=0.0135),
+                                                   None, None, None)),
+]
+
+
+@pytest.mark.parametrize("case", TWO_STEP_CASES, ids=[c[0] for c in TWO_STEP_CASES])
+def test_two_step_launch_equals_single_steps(B, case):
+    """The FP32 form advances pairs of steps in one launch (all but the last
+    step of a call, on lattices this size); the result equals single steps
+    bit for bit: 41 steps in one call against 41 calls of one step."""
+    name, make = case
+    p, phi, Tf0, Ts0 = make()
+    a = B.Lattice(p, phi=phi, Tf0=Tf0, Ts0=Ts0).step(41)
+    b = B.Lattice(p, phi=phi, Tf0=Tf0, Ts0=Ts0)
+    for _ in range(41):
+        b.step(1)
+    ma, mb = a.macros(), b.macros()
+    for k in FIELDS:
+        assert np.array_equal(ma[k], mb[k]), (name, k, np.abs(ma[k] - mb[k]).max())
+    say("two-step launches equal single steps bit for bit:", name)
