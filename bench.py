@@ -132,9 +132,9 @@ def time_form(tag: str, steps: int, warmup: int, inputs):
 
 
 def time_batch(steps: int, warmup: int, autotune: bool = True):
-    """The 256-cavity batch (sides 64..512, seeded parameters), FP32, one
-    launch per step over all lattices (the faster mode; the persistent
-    launch is timed too); aggregate node updates per second."""
+    """The 256-cavity batch (sides 64..512, seeded parameters), FP32, in the
+    default mode (launches over all lattices, two steps per launch; the
+    persistent launch is timed too); aggregate node updates per second."""
     import torch
     from paper_1608_04118_amd import binding as B
     from paper_1608_04118_amd import inputs as I
@@ -167,7 +167,8 @@ def time_batch(steps: int, warmup: int, autotune: bool = True):
     achieved = 152 * nodes / (ms_step * 1e-3) / 1e9
     return dict(ms_per_step=ms_step, mlups=nodes * steps / (ms * 1e-3) / 1e6, achieved_gbs=achieved,
                 frac=achieved / HBM_PEAK_GBS, nodes=nodes, lattices=len(ps), grid=info["grid"],
-                mode="one launch per step", persistent_ms_per_step=ms_persistent,
+                mode="launches over all lattices, two steps per launch but the last of a call",
+                persistent_ms_per_step=ms_persistent,
                 autotune_ms=tuned_ms)
 
 

@@ -475,7 +475,9 @@ def lbm_ltne_batch_destroy(b):
 
 class Batch:
     """Many independent lattices advanced together on the current torch
-    stream (persistent launch by default)."""
+    stream: one launch per step (two steps per launch for the FP32 form when
+    the batch is large enough) by default, or one persistent launch
+    (set_mode(1))."""
 
     def __init__(self, params_list, phi_fields=None, Hv_fields=None, use_torch=True):
         self.ps = [_as_params(p) for p in params_list]

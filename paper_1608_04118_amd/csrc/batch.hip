@@ -18,6 +18,7 @@
 #include "lbm_ltne.h"
 #include "params.hpp"
 #include "reduce_kernels.hpp"
+#include "step2_kernel.hpp"
 #include "step_kernel.hpp"
 
 namespace ltne {
@@ -29,7 +30,7 @@ struct CavityDesc {
   const C* hv;      // per-node interphase coefficient or nullptr
   C* mac;           // macros of the last step (5 planes of nx*ny)
   int tile_begin;   // first entry of this lattice in the combined tile list
-  int pad_;
+  int wave_begin;   // first entry of this lattice in the two-step wavefront list
 };
 
 // Grid barrier state, zeroed by the host before each persistent launch.
@@ -132,6 +133,27 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(
   }
 }
 
+// Two steps of every lattice (FP32 form) in one launch: wavefront w runs
+// strip and chunk w - wave_begin of lattice wave_cav[w], as the
+// single-lattice two-step kernel does.
+template <int F>
+__global__ __launch_bounds__(kBlock) void batch2_kernel(const CavityDesc<float>* __restrict__ cav,
+                                                        const StepConsts<float>* __restrict__ ks,
+                                                        const int* __restrict__ wave_cav, int nwaves, int per_xcd,
+                                                        int parity, uint32_t step) {
+  const int b = blockIdx.x;
+  const int blk = (b & (kXcds - 1)) * per_xcd + (b >> 3);
+  const int wave = blk * (kBlock / 64) + (static_cast<int>(threadIdx.x) >> 6);
+  if (wave >= nwaves) return;  // whole wavefronts
+  const int c = __builtin_amdgcn_readfirstlane(wave_cav[wave]);
+  const StepConsts<float>& k = ks[c];
+  const CavityDesc<float>& d = cav[c];
+  const int local = wave - d.wave_begin;
+  const int nstrips = (k.nx + step2_out(k.px) - 1) / step2_out(k.px);
+  step2_wave<F>(static_cast<const float*>(d.pop[parity]), static_cast<float*>(d.pop[parity ^ 1]), d.phi, d.hv, k,
+                local % nstrips, local / nstrips, step);
+}
+
 }  // namespace ltne
 
 using namespace ltne;
@@ -147,7 +169,8 @@ struct lbm_ltne_batch {
   char* base = nullptr;    // all device memory of the batch
   size_t bytes = 0;
   std::vector<size_t> off_pop0, off_pop1, off_phi, off_hv, off_mac;
-  size_t off_cav = 0, off_consts = 0, off_tiles = 0, off_ctl = 0, off_result = 0;
+  size_t off_cav = 0, off_consts = 0, off_tiles = 0, off_waves = 0, off_ctl = 0, off_result = 0;
+  int nwaves2 = 0;    // wavefronts of a two-step launch over every lattice
   int ntiles = 0;
   int max_tiles = 0;
   int fields = 0;     // kPhiField / kHvField if any lattice has that field
@@ -173,8 +196,9 @@ template <typename C>
 int upload_tables_t(lbm_ltne_batch* b) {
   std::vector<StepConsts<C>> ks(b->n);
   std::vector<CavityDesc<C>> cav(b->n);
-  std::vector<int> tile_cav;
+  std::vector<int> tile_cav, wave_cav;
   tile_cav.reserve(b->max_tiles);
+  wave_cav.reserve(b->nwaves2);
   for (int i = 0; i < b->n; ++i) {
     fill_step_consts(b->p[i], b->d[i], &ks[i]);
     ks[i].tm = make_tiles(b->p[i].nx, b->p[i].ny, b->precision, b->shift[i]);
@@ -185,6 +209,8 @@ int upload_tables_t(lbm_ltne_batch* b) {
     cav[i].mac = reinterpret_cast<C*>(b->base + b->off_mac[i]);
     cav[i].tile_begin = static_cast<int>(tile_cav.size());
     for (int t = 0; t < ks[i].tm.ntiles; ++t) tile_cav.push_back(i);
+    cav[i].wave_begin = static_cast<int>(wave_cav.size());
+    for (int w = 0; w < step2_waves(b->p[i].nx, b->p[i].ny, b->p[i].periodic_x); ++w) wave_cav.push_back(i);
   }
   b->ntiles = static_cast<int>(tile_cav.size());
   HIP_TRY(hipMemcpyAsync(b->base + b->off_consts, ks.data(), ks.size() * sizeof(ks[0]),
@@ -192,6 +218,8 @@ int upload_tables_t(lbm_ltne_batch* b) {
   HIP_TRY(hipMemcpyAsync(b->base + b->off_cav, cav.data(), cav.size() * sizeof(cav[0]),
                          hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipMemcpyAsync(b->base + b->off_tiles, tile_cav.data(), tile_cav.size() * sizeof(int),
+                         hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->base + b->off_waves, wave_cav.data(), wave_cav.size() * sizeof(int),
                          hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
   return LBM_OK;
@@ -238,7 +266,38 @@ int resident_grid(const lbm_ltne_batch* b, int* out) {
 
 constexpr unsigned kSpinLimit = 1u << 24;
 
-int launch_batch(lbm_ltne_batch* b, int nsteps, int macros_last) {
+hipError_t launch_batch2(const lbm_ltne_batch* b, int parity, uint32_t step) {
+  const CavityDesc<float>* cav = reinterpret_cast<const CavityDesc<float>*>(b->base + b->off_cav);
+  const StepConsts<float>* ks = reinterpret_cast<const StepConsts<float>*>(b->base + b->off_consts);
+  const int* waves = reinterpret_cast<const int*>(b->base + b->off_waves);
+  const int nblocks = (b->nwaves2 + kBlock / 64 - 1) / (kBlock / 64);
+  const int per_xcd = (nblocks + kXcds - 1) / kXcds;
+  const dim3 grid(kXcds * per_xcd), block(kBlock);
+  switch (b->fields) {
+    case kPhiField:
+      hipLaunchKernelGGL(batch2_kernel<kPhiField>, grid, block, 0, b->stream, cav, ks, waves, b->nwaves2, per_xcd,
+                         parity, step);
+      break;
+    case kHvField:
+      hipLaunchKernelGGL(batch2_kernel<kHvField>, grid, block, 0, b->stream, cav, ks, waves, b->nwaves2, per_xcd,
+                         parity, step);
+      break;
+    case kPhiField | kHvField:
+      hipLaunchKernelGGL(batch2_kernel<kPhiField | kHvField>, grid, block, 0, b->stream, cav, ks, waves, b->nwaves2,
+                         per_xcd, parity, step);
+      break;
+    default:
+      hipLaunchKernelGGL(batch2_kernel<0>, grid, block, 0, b->stream, cav, ks, waves, b->nwaves2, per_xcd, parity,
+                         step);
+  }
+  return hipGetLastError();
+}
+
+// nsteps steps of every lattice.  Per-step mode: the FP32 form runs pairs
+// of steps in one two-step launch (two_step, and enough wavefronts) except
+// for a last step that writes the macros; the autotuner times single steps
+// only (the tile widths it chooses apply to them).
+int launch_batch(lbm_ltne_batch* b, int nsteps, int macros_last, bool two_step = true) {
   const void* fn = batch_function(b);
   const void* cav = b->base + b->off_cav;
   const void* ks = b->base + b->off_consts;
@@ -252,19 +311,30 @@ int launch_batch(lbm_ltne_batch* b, int nsteps, int macros_last) {
     uint32_t step0 = static_cast<uint32_t>(b->steps + 1);
     void* args[] = {&cav, &ks, &tiles, &ntiles, &nsteps, &parity, &macros_last, &ctl, &spin, &step0};
     HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(b->grid), dim3(kBlock), args, 0, b->stream));
+    b->parity = (b->parity + nsteps) & 1;
   } else {
     const int per = (ntiles + kXcds - 1) / kXcds;
     const int grid = kXcds * per;  // one tile per workgroup per step
-    for (int s = 0; s < nsteps; ++s) {
-      int one = 1;
-      int parity = (b->parity + s) & 1;
-      int mac = (macros_last && s == nsteps - 1) ? 1 : 0;
-      uint32_t step0 = static_cast<uint32_t>(b->steps + 1 + s);
-      void* args[] = {&cav, &ks, &tiles, &ntiles, &one, &parity, &mac, &ctl, &spin, &step0};
-      HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, b->stream));
+    const bool two = two_step && b->precision == LBM_FP32 && b->nwaves2 >= LTNE_STEP2_MIN_WAVES;
+    const int last_single = macros_last ? 1 : 0;
+    int parity = b->parity;
+    for (int s = 0; s < nsteps;) {
+      const uint32_t step0 = static_cast<uint32_t>(b->steps + 1 + s);
+      if (two && s + 2 <= nsteps - last_single) {
+        HIP_TRY(launch_batch2(b, parity, step0));
+        s += 2;
+      } else {
+        int one = 1;
+        int mac = (macros_last && s == nsteps - 1) ? 1 : 0;
+        uint32_t st = step0;
+        void* args[] = {&cav, &ks, &tiles, &ntiles, &one, &parity, &mac, &ctl, &spin, &st};
+        HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, b->stream));
+        s += 1;
+      }
+      parity ^= 1;
     }
+    b->parity = parity;
   }
-  b->parity = (b->parity + nsteps) & 1;
   return LBM_OK;
 }
 
@@ -398,6 +468,7 @@ int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params* ps, const double* co
     int most = 0;  // the tile table must hold the tiles of any width choice
     for (int sh = 6; sh <= 8; ++sh) most = std::max(most, make_tiles(ps[i].nx, ps[i].ny, precision, sh).ntiles);
     b->max_tiles += most;
+    b->nwaves2 += step2_waves(ps[i].nx, ps[i].ny, ps[i].periodic_x);
   }
   const bool cdouble = compute_bytes(precision) == 8;
   b->consts_bytes = (cdouble ? sizeof(StepConsts<double>) : sizeof(StepConsts<float>));
@@ -405,6 +476,7 @@ int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params* ps, const double* co
   b->off_consts = o; o += align_up(n * b->consts_bytes, kAlign);
   b->off_cav = o; o += align_up(n * b->desc_bytes, kAlign);
   b->off_tiles = o; o += align_up(static_cast<size_t>(b->max_tiles) * sizeof(int), kAlign);
+  b->off_waves = o; o += align_up(static_cast<size_t>(b->nwaves2) * sizeof(int), kAlign);
   b->off_ctl = o; o += kAlign;
   b->off_result = o; o += kAlign;
   b->bytes = o;
@@ -532,10 +604,10 @@ int lbm_ltne_batch_autotune(lbm_ltne_batch_t b, int32_t reps, double* ms_per_ste
     int rc = copy_state(false);
     if (rc != LBM_OK) return rc;
     b->parity = parity0;
-    rc = launch_batch(b, 1, 0);  // warm-up
+    rc = launch_batch(b, 1, 0, false);  // warm-up
     if (rc != LBM_OK) return rc;
     HIP_TRY(hipEventRecord(e0, b->stream));
-    rc = launch_batch(b, reps, 0);
+    rc = launch_batch(b, reps, 0, false);
     if (rc != LBM_OK) return rc;
     HIP_TRY(hipEventRecord(e1, b->stream));
     HIP_TRY(hipEventSynchronize(e1));

@@ -130,22 +130,16 @@ hipError_t launch_step(const lbm_ltne* h, int mode, int64_t step, const void* sr
   }
 }
 
-#ifndef LTNE_STEP2_ROWS
-#define LTNE_STEP2_ROWS 8
-#endif
-#ifndef LTNE_STEP2_MIN_WAVES
-#define LTNE_STEP2_MIN_WAVES 1024
-#endif
 
 // Geometry of the two-step kernel: strips of 64 lanes (63 - halo output
-// columns), chunks of LTNE_STEP2_ROWS rows, four wavefronts per workgroup,
+// columns), chunks of kStep2Rows rows, four wavefronts per workgroup,
 // workgroups dealt to the XCDs in contiguous ranges.
 Step2Map step2_map(const lbm_ltne_params& p) {
   Step2Map m{};
-  m.halo = p.periodic_x ? 1 : 2;
-  m.out = 63 - m.halo;
+  m.halo = step2_halo(p.periodic_x);
+  m.out = step2_out(p.periodic_x);
   m.nstrips = (p.nx + m.out - 1) / m.out;
-  m.rows = LTNE_STEP2_ROWS;
+  m.rows = kStep2Rows;
   m.nchunks = (p.ny + m.rows - 1) / m.rows;
   m.nwaves = m.nstrips * m.nchunks;
   const int nblocks = (m.nwaves + kBlock / 64 - 1) / (kBlock / 64);

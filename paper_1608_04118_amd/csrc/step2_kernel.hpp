@@ -23,6 +23,26 @@
 
 namespace ltne {
 
+// Rows per chunk: short chunks recompute more halo rows but give more
+// wavefronts in flight (measured best at 8 on the 8192^2 layer).
+#ifndef LTNE_STEP2_ROWS
+#define LTNE_STEP2_ROWS 8
+#endif
+constexpr int kStep2Rows = LTNE_STEP2_ROWS;
+// Two-step launches need this many wavefronts to hide the serial chain of
+// rows each one runs; with fewer, single steps are faster (512^2: 576).
+#ifndef LTNE_STEP2_MIN_WAVES
+#define LTNE_STEP2_MIN_WAVES 1024
+#endif
+
+// Lanes left of a strip's first output column: one on a periodic x axis,
+// two with x walls (a wall node pulls from two columns inward).
+__host__ __device__ constexpr int step2_halo(int periodic_x) { return periodic_x ? 1 : 2; }
+__host__ __device__ constexpr int step2_out(int periodic_x) { return 63 - step2_halo(periodic_x); }
+__host__ __device__ constexpr int step2_waves(int nx, int ny, int periodic_x) {
+  return ((nx + step2_out(periodic_x) - 1) / step2_out(periodic_x)) * ((ny + kStep2Rows - 1) / kStep2Rows);
+}
+
 // Launch geometry of the two-step kernel.
 struct Step2Map {
   int halo;     // lanes left of the first output column (1 or 2)
@@ -56,22 +76,18 @@ struct RegPull {
   }
 };
 
+// One wavefront's strip and chunk of a lattice.
 template <int F>
-__global__ __launch_bounds__(kBlock) void step2_kernel(const float* __restrict__ src, float* __restrict__ dst,
-                                                       const float* __restrict__ phi_field,
-                                                       const float* __restrict__ hv_field,
-                                                       const StepConsts<float> k, const Step2Map m,
-                                                       const uint32_t step) {
-  const int b = blockIdx.x;
-  const int blk = (b & (kXcds - 1)) * m.per_xcd + (b >> 3);
-  const int wave = blk * (kBlock / 64) + (static_cast<int>(threadIdx.x) >> 6);
-  if (wave >= m.nwaves) return;  // whole wavefronts
+__device__ __forceinline__ void step2_wave(const float* __restrict__ src, float* __restrict__ dst,
+                                           const float* __restrict__ phi_field, const float* __restrict__ hv_field,
+                                           const StepConsts<float>& k, const int strip, const int chunk,
+                                           const uint32_t step) {
   const int lane = static_cast<int>(threadIdx.x) & 63;
   const int nx = k.nx, ny = k.ny;
-  const int strip = wave % m.nstrips, chunk = wave / m.nstrips;
-  const int x0 = strip * m.out;
+  const int halo = step2_halo(k.px), out = step2_out(k.px), rows = kStep2Rows;
+  const int x0 = strip * out;
   // column of this lane at time t + 1
-  int col = x0 - m.halo + lane;
+  int col = x0 - halo + lane;
   bool colok = true;
   if (k.px) {
     col %= nx;
@@ -80,11 +96,11 @@ __global__ __launch_bounds__(kBlock) void step2_kernel(const float* __restrict__
     colok = col >= 0 && col < nx;
   }
   // output column and the column offset of its pulls (x walls pull inward)
-  const int xo = x0 - m.halo + lane;
-  const bool outlane = lane >= m.halo && lane < m.halo + m.out && xo < nx;
+  const int xo = x0 - halo + lane;
+  const bool outlane = lane >= halo && lane < halo + out && xo < nx;
   const int dx = (!k.px && xo == 0) ? 1 : ((!k.px && xo == nx - 1) ? -1 : 0);
   // rows of this chunk; a wall row is updated with its inward neighbour row
-  int y_lo = chunk * m.rows, y_hi = y_lo + m.rows < ny ? y_lo + m.rows : ny;
+  int y_lo = chunk * rows, y_hi = y_lo + rows < ny ? y_lo + rows : ny;
   if (!k.py) {
     y_lo = y_lo > 1 ? y_lo : 1;
     y_hi = y_hi < ny - 1 ? y_hi : ny - 1;
@@ -165,6 +181,19 @@ __global__ __launch_bounds__(kBlock) void step2_kernel(const float* __restrict__
       wb[i] = wc[i];
     }
   }
+}
+
+template <int F>
+__global__ __launch_bounds__(kBlock) void step2_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                                                       const float* __restrict__ phi_field,
+                                                       const float* __restrict__ hv_field,
+                                                       const StepConsts<float> k, const Step2Map m,
+                                                       const uint32_t step) {
+  const int b = blockIdx.x;
+  const int blk = (b & (kXcds - 1)) * m.per_xcd + (b >> 3);
+  const int wave = blk * (kBlock / 64) + (static_cast<int>(threadIdx.x) >> 6);
+  if (wave >= m.nwaves) return;  // whole wavefronts
+  step2_wave<F>(src, dst, phi_field, hv_field, k, wave % m.nstrips, wave / m.nstrips, step);
 }
 
 }  // namespace ltne

@@ -130,3 +130,28 @@ def test_batch_256_cavities(B, oracle):
         say("cavity", i, "n", ps[i]["nx"], "tau_min %.4f" % tau_min, "errors", ["%.2e" % e for e in errs])
         if tau_min > 0.55:
             assert max(errs) < 1e-5
+
+
+def test_two_step_batch_equals_single(B):
+    """FP32 batches with enough wavefronts run pairs of steps per launch
+    (the batched two-step kernel): every lattice still equals the same
+    lattice run alone, one step at a time, bit for bit."""
+    r = np.random.default_rng(9)
+    ps = [I.cavity_small(nx=n, ny=m, precision=I.FP32, Ra=float(ra), phi=float(ph), Hv=float(hv))
+          for n, m, ra, ph, hv in ((512, 512, 1e5, 0.6, 10.0), (480, 300, 3e4, 0.45, 200.0),
+                                   (333, 417, 2e5, 0.7, 1.0), (450, 450, 1e4, 0.55, 40.0))]
+    ps.append(I.throughput(n=500, ny=257)[0])  # periodic x, heated from below
+    ps.append(I.cavity_small(nx=400, ny=400, precision=I.FP32, Ra=1e5, thermal_correction=1, pore_size=0.0135))
+    phis = [None] * len(ps)
+    phis[2] = np.clip(0.7 + 0.1 * r.standard_normal((417, 333)), 0.4, 0.9)
+    bt = B.Batch(ps, phi_fields=phis)
+    bt.set_mode(0)
+    bt.step(31).step(10)
+    for i, p in enumerate(ps):
+        single = B.Lattice(p, phi=phis[i])
+        for _ in range(41):
+            single.step(1)
+        a, b = bt.macros(i), single.macros()
+        for k in FIELDS:
+            assert np.array_equal(a[k], b[k]), (i, k, np.abs(a[k] - b[k]).max())
+    say("two-step batch of", len(ps), "equals single steps bit for bit")
