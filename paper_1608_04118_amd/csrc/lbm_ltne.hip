@@ -142,7 +142,7 @@ Step2Map step2_map(const lbm_ltne_params& p) {
   m.rows = kStep2Rows;
   m.nchunks = (p.ny + m.rows - 1) / m.rows;
   m.nwaves = m.nstrips * m.nchunks;
-  const int nblocks = (m.nwaves + kBlock / 64 - 1) / (kBlock / 64);
+  const int nblocks = (m.nwaves + kStep2Block / 64 - 1) / (kStep2Block / 64);
   m.per_xcd = (nblocks + kXcds - 1) / kXcds;
   return m;
 }
@@ -150,7 +150,7 @@ Step2Map step2_map(const lbm_ltne_params& p) {
 // Two steps of the FP32 form in one launch (no macro output).
 hipError_t launch_step2(const lbm_ltne* h, int64_t step, const void* src, void* dst) {
   const Step2Map m = step2_map(h->p);
-  const dim3 grid(kXcds * m.per_xcd), block(kBlock);
+  const dim3 grid(kXcds * m.per_xcd), block(kStep2Block);
   const uint32_t st = static_cast<uint32_t>(step);
   const float* s = static_cast<const float*>(src);
   float* d = static_cast<float*>(dst);

@@ -29,6 +29,20 @@ namespace ltne {
 #define LTNE_STEP2_ROWS 8
 #endif
 constexpr int kStep2Rows = LTNE_STEP2_ROWS;
+// Threads per workgroup of the two-step kernels (whole wavefronts; each
+// wavefront works on its own strip and chunk).
+#ifndef LTNE_STEP2_BLOCK
+#define LTNE_STEP2_BLOCK 256
+#endif
+constexpr int kStep2Block = LTNE_STEP2_BLOCK;
+static_assert(kStep2Block % 64 == 0 && kStep2Block <= 1024, "whole wavefronts per workgroup");
+// Stores of the two-step kernels: plain, so the L2 merges the partial cache
+// lines written by neighbouring strips (62 or 61 columns wide) before they go
+// to HBM; non-temporal stores were 5% slower on the 8192^2 layer.
+#ifndef LTNE_STEP2_NT_STORE
+#define LTNE_STEP2_NT_STORE 0
+#endif
+constexpr bool kStep2NtStore = LTNE_STEP2_NT_STORE != 0;
 // Two-step launches need this many wavefronts to hide the serial chain of
 // rows each one runs; with fewer, single steps are faster (512^2: 576).
 #ifndef LTNE_STEP2_MIN_WAVES
@@ -165,7 +179,7 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
     }
     if (outlane) {
       const RegPull<float> rpull{g};
-      GlobalPut<float, float> put{dst};
+      GlobalPut<float, float, kStep2NtStore> put{dst};
       node_update_with<float, float, F>(xo, y, rpull, put, phi_field, hv_field, nullptr, nullptr, nullptr, k,
                                         step + 1u, nullptr);
       if (!k.py && y == 1)
@@ -184,14 +198,14 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
 }
 
 template <int F>
-__global__ __launch_bounds__(kBlock) void step2_kernel(const float* __restrict__ src, float* __restrict__ dst,
+__global__ __launch_bounds__(kStep2Block) void step2_kernel(const float* __restrict__ src, float* __restrict__ dst,
                                                        const float* __restrict__ phi_field,
                                                        const float* __restrict__ hv_field,
                                                        const StepConsts<float> k, const Step2Map m,
                                                        const uint32_t step) {
   const int b = blockIdx.x;
   const int blk = (b & (kXcds - 1)) * m.per_xcd + (b >> 3);
-  const int wave = blk * (kBlock / 64) + (static_cast<int>(threadIdx.x) >> 6);
+  const int wave = blk * (kStep2Block / 64) + (static_cast<int>(threadIdx.x) >> 6);
   if (wave >= m.nwaves) return;  // whole wavefronts
   step2_wave<F>(src, dst, phi_field, hv_field, k, wave % m.nstrips, wave / m.nstrips, step);
 }

@@ -52,9 +52,12 @@ __device__ __forceinline__ C load_pop(const S* __restrict__ p, C inv_scale) {
   }
 }
 
-template <typename S>
+// NT: non-temporal store (the single-step kernels, whose rows are written
+// whole by one wavefront); the two-step kernels store plainly, so the L2
+// merges the partial cache lines that neighbouring strips write.
+template <bool NT = kNtStore, typename S>
 __device__ __forceinline__ void store_raw(S* __restrict__ p, S v) {
-  if constexpr (kNtStore) {
+  if constexpr (NT) {
     __builtin_nontemporal_store(v, p);
   } else {
     *p = v;
@@ -74,14 +77,14 @@ constexpr bool kStochastic = !std::is_same<S, C>::value;
 
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
-template <typename S, typename C>
+template <bool NT = kNtStore, typename S, typename C>
 __device__ __forceinline__ void store_pop(S* __restrict__ p, C v, C scale, uint32_t r) {
   if constexpr (std::is_same<S, _Float16>::value) {
     // binary32 -> binary16: the gfx950 stochastic-rounding convert adds the
     // top 13 bits of r to the 13 discarded significand bits
     half2_t h = __builtin_nondeterministic_value(h);
     h = __builtin_amdgcn_cvt_sr_f16_f32(h, static_cast<float>(v * scale), r, false);
-    store_raw(p, h[0]);
+    store_raw<NT>(p, h[0]);
   } else if constexpr (std::is_same<S, float>::value && std::is_same<C, double>::value) {
     // binary64 -> binary32: 29 discarded significand bits, 16 random ones
     // added at their top
@@ -89,11 +92,11 @@ __device__ __forceinline__ void store_pop(S* __restrict__ p, C v, C scale, uint3
     unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v)) +
                            (static_cast<unsigned long long>(r >> 16) << 13);
     u &= ~0x1fffffffull;
-    store_raw(p, static_cast<float>(__longlong_as_double(static_cast<long long>(u))));  // exact
+    store_raw<NT>(p, static_cast<float>(__longlong_as_double(static_cast<long long>(u))));  // exact
   } else {
     (void)scale;
     (void)r;
-    store_raw(p, static_cast<S>(v));
+    store_raw<NT>(p, static_cast<S>(v));
   }
 }
 
@@ -103,18 +106,18 @@ __device__ __forceinline__ void store_pop(S* __restrict__ p, C v, C scale, uint3
 // bits of its random operand to the 13 discarded significand bits, into the
 // two halves of one register (h carries that register from pair to pair, so
 // no register is cleared for it).
-template <typename S, typename C>
+template <bool NT = kNtStore, typename S, typename C>
 __device__ __forceinline__ void store_pair(S* __restrict__ pa, C va, C sa, S* __restrict__ pb, C vb, C sb,
                                            uint32_t w, half2_t& h) {
   if constexpr (std::is_same<S, _Float16>::value) {
     h = __builtin_amdgcn_cvt_sr_f16_f32(h, static_cast<float>(va * sa), w << 16, false);
     h = __builtin_amdgcn_cvt_sr_f16_f32(h, static_cast<float>(vb * sb), w, true);
-    store_raw(pa, h[0]);
-    store_raw(pb, h[1]);
+    store_raw<NT>(pa, h[0]);
+    store_raw<NT>(pb, h[1]);
   } else {
     (void)h;
-    store_pop(pa, va, sa, w << 16);
-    store_pop(pb, vb, sb, w);
+    store_pop<NT>(pa, va, sa, w << 16);
+    store_pop<NT>(pb, vb, sb, w);
   }
 }
 
@@ -212,8 +215,8 @@ struct GlobalPull {
 };
 
 // Put: the node's own 19 slots of the destination buffer, in pairs that
-// share one random word (see store_pair).
-template <typename S, typename C>
+// share one random word (see store_pair); NT selects non-temporal stores.
+template <typename S, typename C, bool NT = kNtStore>
 struct GlobalPut {
   S* __restrict__ dst;
   S* __restrict__ drow = nullptr;
@@ -225,9 +228,9 @@ struct GlobalPut {
     x = x_;
   }
   __device__ __forceinline__ void pair(int i, C va, C sa, int j, C vb, C sb, uint32_t w, half2_t& h) {
-    store_pair(at(drow + i * P, x), va, sa, at(drow + j * P, x), vb, sb, w, h);
+    store_pair<NT>(at(drow + i * P, x), va, sa, at(drow + j * P, x), vb, sb, w, h);
   }
-  __device__ __forceinline__ void single(int i, C v, C s, uint32_t r) { store_pop(at(drow + i * P, x), v, s, r); }
+  __device__ __forceinline__ void single(int i, C v, C s, uint32_t r) { store_pop<NT>(at(drow + i * P, x), v, s, r); }
 };
 
 template <typename S, typename C, int F, class Pull, class Put>
