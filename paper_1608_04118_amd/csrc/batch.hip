@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kStep2Block) void batch2_kernel(const CavityDesc<fl
   const int local = wave - d.wave_begin;
   const int nstrips = (k.nx + step2_out(k.px) - 1) / step2_out(k.px);
   step2_wave<F>(static_cast<const float*>(d.pop[parity]), static_cast<float*>(d.pop[parity ^ 1]), d.phi, d.hv, k,
-                local % nstrips, local / nstrips, step);
+                local % nstrips, local / nstrips, kBatch2Rows, step);
 }
 
 }  // namespace ltne
@@ -171,6 +171,7 @@ struct lbm_ltne_batch {
   std::vector<size_t> off_pop0, off_pop1, off_phi, off_hv, off_mac;
   size_t off_cav = 0, off_consts = 0, off_tiles = 0, off_waves = 0, off_ctl = 0, off_result = 0;
   int nwaves2 = 0;    // wavefronts of a two-step launch over every lattice
+  int nwaves2_min = 0;  // the same at the smallest chunk height (decides whether to use it)
   int ntiles = 0;
   int max_tiles = 0;
   int fields = 0;     // kPhiField / kHvField if any lattice has that field
@@ -210,7 +211,8 @@ int upload_tables_t(lbm_ltne_batch* b) {
     cav[i].tile_begin = static_cast<int>(tile_cav.size());
     for (int t = 0; t < ks[i].tm.ntiles; ++t) tile_cav.push_back(i);
     cav[i].wave_begin = static_cast<int>(wave_cav.size());
-    for (int w = 0; w < step2_waves(b->p[i].nx, b->p[i].ny, b->p[i].periodic_x); ++w) wave_cav.push_back(i);
+    for (int w = 0; w < step2_waves(b->p[i].nx, b->p[i].ny, b->p[i].periodic_x, kBatch2Rows); ++w)
+      wave_cav.push_back(i);
   }
   b->ntiles = static_cast<int>(tile_cav.size());
   HIP_TRY(hipMemcpyAsync(b->base + b->off_consts, ks.data(), ks.size() * sizeof(ks[0]),
@@ -315,7 +317,7 @@ int launch_batch(lbm_ltne_batch* b, int nsteps, int macros_last, bool two_step =
   } else {
     const int per = (ntiles + kXcds - 1) / kXcds;
     const int grid = kXcds * per;  // one tile per workgroup per step
-    const bool two = two_step && b->precision == LBM_FP32 && b->nwaves2 >= LTNE_STEP2_MIN_WAVES;
+    const bool two = two_step && b->precision == LBM_FP32 && b->nwaves2_min >= LTNE_STEP2_MIN_WAVES;
     const int last_single = macros_last ? 1 : 0;
     int parity = b->parity;
     for (int s = 0; s < nsteps;) {
@@ -468,7 +470,8 @@ int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params* ps, const double* co
     int most = 0;  // the tile table must hold the tiles of any width choice
     for (int sh = 6; sh <= 8; ++sh) most = std::max(most, make_tiles(ps[i].nx, ps[i].ny, precision, sh).ntiles);
     b->max_tiles += most;
-    b->nwaves2 += step2_waves(ps[i].nx, ps[i].ny, ps[i].periodic_x);
+    b->nwaves2 += step2_waves(ps[i].nx, ps[i].ny, ps[i].periodic_x, kBatch2Rows);
+    b->nwaves2_min += step2_waves(ps[i].nx, ps[i].ny, ps[i].periodic_x, kStep2MinRows);
   }
   const bool cdouble = compute_bytes(precision) == 8;
   b->consts_bytes = (cdouble ? sizeof(StepConsts<double>) : sizeof(StepConsts<float>));

@@ -132,14 +132,14 @@ hipError_t launch_step(const lbm_ltne* h, int mode, int64_t step, const void* sr
 
 
 // Geometry of the two-step kernel: strips of 64 lanes (63 - halo output
-// columns), chunks of kStep2Rows rows, four wavefronts per workgroup,
+// columns), chunks of step2_rows() rows, kStep2Block / 64 wavefronts per workgroup,
 // workgroups dealt to the XCDs in contiguous ranges.
 Step2Map step2_map(const lbm_ltne_params& p) {
   Step2Map m{};
   m.halo = step2_halo(p.periodic_x);
   m.out = step2_out(p.periodic_x);
   m.nstrips = (p.nx + m.out - 1) / m.out;
-  m.rows = kStep2Rows;
+  m.rows = step2_rows(p.nx, p.ny, p.periodic_x);
   m.nchunks = (p.ny + m.rows - 1) / m.rows;
   m.nwaves = m.nstrips * m.nchunks;
   const int nblocks = (m.nwaves + kStep2Block / 64 - 1) / (kStep2Block / 64);
@@ -331,7 +331,8 @@ int lbm_ltne_step(lbm_ltne_t h, int64_t nsteps) {
   // two steps per launch where the lattice gives the two-step kernel enough
   // wavefronts to hide its latency (each wavefront runs a serial chain of
   // rows); small lattices run faster one step at a time
-  if (h->p.precision == LBM_FP32 && step2_map(h->p).nwaves >= LTNE_STEP2_MIN_WAVES) {
+  if (h->p.precision == LBM_FP32 &&
+      step2_waves(h->p.nx, h->p.ny, h->p.periodic_x, kStep2MinRows) >= LTNE_STEP2_MIN_WAVES) {
     // pairs of steps in one launch while more than the last step (which
     // also writes the macros) remain
     for (; s + 2 <= nsteps - 1; s += 2) {

@@ -23,12 +23,21 @@
 
 namespace ltne {
 
-// Rows per chunk: short chunks recompute more halo rows but give more
-// wavefronts in flight (measured best at 8 on the 8192^2 layer).
-#ifndef LTNE_STEP2_ROWS
-#define LTNE_STEP2_ROWS 8
+// Rows per chunk.  A chunk recomputes two halo rows at the intermediate time
+// level, so taller chunks do less redundant work but leave fewer wavefronts
+// in flight.  A single lattice takes the tallest of kStep2RowChoices that
+// still yields kStep2TargetWaves wavefronts; a batch of lattices (many small
+// ones) uses kBatch2Rows.  LTNE_STEP2_ROWS forces one height (experiments).
+constexpr int kStep2RowChoices[] = {32, 24, 16, 12, 8};
+constexpr int kStep2MinRows = 8;
+#ifndef LTNE_STEP2_TARGET_WAVES
+#define LTNE_STEP2_TARGET_WAVES 16384
 #endif
-constexpr int kStep2Rows = LTNE_STEP2_ROWS;
+constexpr int kStep2TargetWaves = LTNE_STEP2_TARGET_WAVES;
+#ifndef LTNE_BATCH2_ROWS
+#define LTNE_BATCH2_ROWS 16
+#endif
+constexpr int kBatch2Rows = LTNE_BATCH2_ROWS;
 // Threads per workgroup of the two-step kernels (whole wavefronts; each
 // wavefront works on its own strip and chunk).
 #ifndef LTNE_STEP2_BLOCK
@@ -43,8 +52,9 @@ static_assert(kStep2Block % 64 == 0 && kStep2Block <= 1024, "whole wavefronts pe
 #define LTNE_STEP2_NT_STORE 0
 #endif
 constexpr bool kStep2NtStore = LTNE_STEP2_NT_STORE != 0;
-// Two-step launches need this many wavefronts to hide the serial chain of
-// rows each one runs; with fewer, single steps are faster (512^2: 576).
+// Two-step launches need this many wavefronts at the smallest chunk height
+// to hide the serial chain of rows each one runs; with fewer, single steps
+// are faster (512^2: 576).
 #ifndef LTNE_STEP2_MIN_WAVES
 #define LTNE_STEP2_MIN_WAVES 1024
 #endif
@@ -53,8 +63,19 @@ constexpr bool kStep2NtStore = LTNE_STEP2_NT_STORE != 0;
 // two with x walls (a wall node pulls from two columns inward).
 __host__ __device__ constexpr int step2_halo(int periodic_x) { return periodic_x ? 1 : 2; }
 __host__ __device__ constexpr int step2_out(int periodic_x) { return 63 - step2_halo(periodic_x); }
-__host__ __device__ constexpr int step2_waves(int nx, int ny, int periodic_x) {
-  return ((nx + step2_out(periodic_x) - 1) / step2_out(periodic_x)) * ((ny + kStep2Rows - 1) / kStep2Rows);
+__host__ __device__ constexpr int step2_waves(int nx, int ny, int periodic_x, int rows) {
+  return ((nx + step2_out(periodic_x) - 1) / step2_out(periodic_x)) * ((ny + rows - 1) / rows);
+}
+// Chunk height of a single lattice's two-step launches.
+inline int step2_rows(int nx, int ny, int periodic_x) {
+#ifdef LTNE_STEP2_ROWS
+  (void)nx, (void)ny, (void)periodic_x;
+  return LTNE_STEP2_ROWS;
+#else
+  for (int r : kStep2RowChoices)
+    if (step2_waves(nx, ny, periodic_x, r) >= kStep2TargetWaves) return r;
+  return kStep2MinRows;
+#endif
 }
 
 // Launch geometry of the two-step kernel.
@@ -95,10 +116,10 @@ template <int F>
 __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float* __restrict__ dst,
                                            const float* __restrict__ phi_field, const float* __restrict__ hv_field,
                                            const StepConsts<float>& k, const int strip, const int chunk,
-                                           const uint32_t step) {
+                                           const int rows, const uint32_t step) {
   const int lane = static_cast<int>(threadIdx.x) & 63;
   const int nx = k.nx, ny = k.ny;
-  const int halo = step2_halo(k.px), out = step2_out(k.px), rows = kStep2Rows;
+  const int halo = step2_halo(k.px), out = step2_out(k.px);
   const int x0 = strip * out;
   // column of this lane at time t + 1
   int col = x0 - halo + lane;
@@ -207,7 +228,7 @@ __global__ __launch_bounds__(kStep2Block) void step2_kernel(const float* __restr
   const int blk = (b & (kXcds - 1)) * m.per_xcd + (b >> 3);
   const int wave = blk * (kStep2Block / 64) + (static_cast<int>(threadIdx.x) >> 6);
   if (wave >= m.nwaves) return;  // whole wavefronts
-  step2_wave<F>(src, dst, phi_field, hv_field, k, wave % m.nstrips, wave / m.nstrips, step);
+  step2_wave<F>(src, dst, phi_field, hv_field, k, wave % m.nstrips, wave / m.nstrips, m.rows, step);
 }
 
 }  // namespace ltne

@@ -271,6 +271,14 @@ TWO_STEP_CASES = [
     ("cavity 1024x1024, both extensions", lambda: (I.cavity_small(nx=1024, ny=1024, precision=I.FP32, Ra=1e5,
                                                                   thermal_correction=1, pore_size=0.0135),
                                                    None, None, None)),
+    # lattices that take taller chunks (the tallest of 32, 24, 16, 12 rows
+    # giving 16384 wavefronts): 12 rows with x walls (66 strips x 251
+    # chunks), 24 rows periodic (97 x 209) and the 8192^2 layer, 32 rows
+    # (133 x 256), ragged last chunks in the first two
+    ("cavity 4000x3004, tall chunks", lambda: (I.cavity_small(nx=4000, ny=3004, precision=I.FP32, Ra=1e6),
+                                                None, None, None)),
+    ("layer 6000x5000, tall chunks", lambda: I.throughput(n=6000, ny=5000)),
+    ("layer 8192x8192, tall chunks", lambda: I.throughput(n=8192)),
 ]
 
 
