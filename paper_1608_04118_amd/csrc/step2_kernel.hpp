@@ -1,7 +1,7 @@
 // Two fused time steps per launch for the FP32 form (binary32 storage and
-// arithmetic).  The single-step kernel is bound by memory traffic at about
-// 450 vector instructions per 156 bytes; computing two steps per pass over
-// the populations halves the traffic per lattice-node update.
+// arithmetic).  The single-step kernel is bound by memory traffic at 410
+// vector instructions per 156 bytes; computing two steps per pass over the
+// populations halves the traffic per lattice-node update.
 //
 // Each wavefront owns a strip of columns and a chunk of rows and marches
 // down the rows.  Lane l holds column x0 - H + l (H = 1 on a periodic x axis,
