@@ -283,8 +283,9 @@ __device__ __forceinline__ void node_update_with(
     const C thf = init_tf ? init_tf[ic] : k.theta_init_f;
     const C ths = init_ts ? init_ts[ic] : k.theta_init_s;
     const C hv = k.hv_corr ? C(0) : hv_c * k.hvf;  // the correlation gives 0 at rest
-    const C d0 = C(0.5) * hv * dev_rcp(phi_c);
-    const C d1 = C(0.5) * hv * k.inv_sigma * dev_rcp(C(1) - phi_c);
+    const C rpp = dev_rcp(phi_c * (C(1) - phi_c));  // as in the step below
+    const C d0 = C(0.5) * hv * ((C(1) - phi_c) * rpp);
+    const C d1 = C(0.5) * hv * k.inv_sigma * (phi_c * rpp);
     const C srf = C(2) * d0 * (ths - thf) + k.Qf;
     const C srs = C(2) * d1 * (thf - ths) + k.Qs;
     const C w0 = C(1) - k.varpi, w1 = C(0.25) * k.varpi;
@@ -326,9 +327,12 @@ __device__ __forceinline__ void node_update_with(
     // which needs h_v): h_v / (rho c_p)_f = corr_a Re^0.644, Re = corr_b u_m
     hv = k.corr_a * pow_0644(k.corr_b * dev_sqrt(jx * jx + jy * jy) * inv_rho);
   }
-  const C rphi_c = dev_rcp(phi_c);
+  // 1 / phi and 1 / (1 - phi) from one reciprocal (transcendentals issue at a
+  // fraction of the rate of multiplies)
+  const C rpp = dev_rcp(phi_c * (C(1) - phi_c));
+  const C rphi_c = (C(1) - phi_c) * rpp;
   C d0 = C(0.5) * hv * rphi_c;
-  C d1 = C(0.5) * hv * k.inv_sigma * dev_rcp(C(1) - phi_c);
+  C d1 = C(0.5) * hv * k.inv_sigma * (phi_c * rpp);
   const C sgf = ((a0 + a1) + (a2 + a3)) + a4;
   const C sgh = ((b0 + b1) + (b2 + b3)) + b4;  // sum g_s - sum g_f
   const C A = sgf + C(0.5) * k.Qf;
@@ -364,7 +368,7 @@ __device__ __forceinline__ void node_update_with(
     const C rden = dev_rcp(den);
     ux = vx * rden;
     uy = vy * rden;
-    const C um = dev_sqrt(ux * ux + uy * uy);
+    const C um = vm * rden;  // |u| = |v| / den (Eq. 20)
     const C drag = -phi_c * (k.nu_over_K + Fphi * k.inv_sqrtK * um);
     rFx = rho * (drag * ux + phi_c * Gx);
     rFy = rho * (drag * uy + phi_c * Gy);
@@ -433,11 +437,12 @@ __device__ __forceinline__ void node_update_with(
     // Prescribed wall values; coefficients at the wall node itself.
     const int ib = y * nx + x;
     phi = (F & kPhiField) ? phi_field[ib] : k.phi_u;
-    rphi = dev_rcp(phi);
+    const C rppb = dev_rcp(phi * (C(1) - phi));
+    rphi = (C(1) - phi) * rppb;
     // (u = 0 at the wall: the correlation gives h_v = 0 there)
     const C hvb = k.hv_corr ? C(0) : ((F & kHvField) ? hv_field[ib] : k.hv_u) * k.hvf;
     d0 = C(0.5) * hvb * rphi;
-    d1 = C(0.5) * hvb * k.inv_sigma * dev_rcp(C(1) - phi);
+    d1 = C(0.5) * hvb * k.inv_sigma * (phi * rppb);
     thf = thfb;
     ths = thsb;
     D = Db;
