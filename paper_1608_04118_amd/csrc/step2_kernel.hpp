@@ -1,5 +1,5 @@
 // Two fused time steps per launch for the FP32 form (binary32 storage and
-// arithmetic).  The single-step kernel is bound by memory traffic at 410
+// arithmetic).  The single-step kernel is bound by memory traffic at 395
 // vector instructions per 156 bytes; computing two steps per pass over the
 // populations halves the traffic per lattice-node update.
 //
