@@ -176,7 +176,11 @@ int lbm_ltne_create(const lbm_ltne_params *p, const double *phi_field, const dou
 
 /* Advances nsteps >= 0 time steps (asynchronous).  Each step is one fused
  * launch: pull streaming, wall reconstruction, macros, the three collisions,
- * store.  The macros of the last step are kept for lbm_ltne_macros,
+ * store.  In the FP32 form, on lattices that yield at least 1024 strips of
+ * 62 (periodic x) or 61 columns by 8 rows, all but the last step of a call
+ * advance in pairs, two steps per launch with the intermediate time level
+ * kept on chip; the result equals single steps bit for bit.  The macros of
+ * the last step are kept for lbm_ltne_macros,
  * lbm_ltne_nusselt and lbm_ltne_diagnostics; the residual compares them with
  * the macros kept by the previous call. */
 int lbm_ltne_step(lbm_ltne_t h, int64_t nsteps);
@@ -244,7 +248,9 @@ int lbm_ltne_destroy(lbm_ltne_t h);
 /*
  * Batched lattices: n independent lattices of uneven size and parameters
  * (one precision per batch) advanced together.  By default (mode 0) a batch
- * step is one launch over the combined tile list of all lattices; mode 1
+ * step is one launch over the combined tile list of all lattices (FP32
+ * batches of at least 1024 strips of 8 rows: pairs of steps per launch, as in
+ * lbm_ltne_step, with 16-row chunks); mode 1
  * runs all steps of a call in one persistent cooperative launch with a
  * grid-wide barrier between steps (every barrier wait is bounded; a timeout
  * is reported as LBM_EHIP by the next synchronizing call).  Every lattice
