@@ -476,8 +476,17 @@ __device__ __forceinline__ void node_update_with(
   uint32_t rb[10];
   if constexpr (kStochastic<S, C>) {
     const uint32_t base = mix32(static_cast<uint32_t>(io) ^ mix32(step * 0x9e3779b9u + 0x632be5abu));
+    // word j: one xor-shift / multiply / xor-shift round of base + j K (the
+    // full two-multiply mix is kept for base; a second multiply per word cost
+    // 2% of the binary16 step and adds nothing the rounding can use)
 #pragma unroll
-    for (int j = 0; j < 10; ++j) rb[j] = mix32(base + static_cast<uint32_t>(j) * 0x85ebca77u);
+    for (int j = 0; j < 10; ++j) {
+      uint32_t w = base + static_cast<uint32_t>(j) * 0x85ebca77u;
+      w ^= w >> 16;
+      w *= 0x7feb352du;
+      w ^= w >> 15;
+      rb[j] = w;
+    }
   } else {
 #pragma unroll
     for (int j = 0; j < 10; ++j) rb[j] = 0u;
