@@ -1,0 +1,96 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU contract, the kernel
+source hash that guards committed counter runs, and the conversion of
+rocprofv3 byte counters into HBM bytes per launch."""
+import csv
+import json
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout.strip() == ""  # no JSON line
+
+
+def _copy_sources(dst):
+    for s in bench.KERNEL_SOURCES:
+        os.makedirs(os.path.dirname(os.path.join(dst, s)), exist_ok=True)
+        shutil.copy(os.path.join(ROOT, s), os.path.join(dst, s))
+
+
+def test_kernel_hash_ignores_comments_only(tmp_path, monkeypatch):
+    _copy_sources(tmp_path)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.kernel_hash()
+    assert h0 == bench.kernel_hash()
+    p = tmp_path / "paper_1608_04118_amd" / "csrc" / "step2_kernel.hpp"
+    text = p.read_text()
+    # a new comment line and a changed trailing comment: same kernel, same hash
+    p.write_text("// a remark\n\n" + text.replace("#pragma once", "#pragma once  // guard", 1))
+    assert bench.kernel_hash() == h0
+    # a code change: different hash
+    p.write_text(text.replace("#pragma once", "#pragma once\nstatic const int unused_probe = 1;", 1))
+    assert bench.kernel_hash() != h0
+
+
+def test_measured_traffic_only_for_current_sources(tmp_path, monkeypatch):
+    _copy_sources(tmp_path)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    rec = {"f32": {"kernel_hash": bench.kernel_hash(), "bytes_per_launch": 11.5e9}}
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    assert bench.measured_traffic("f32") == 11.5e9
+    assert bench.measured_traffic("f64") is None
+    rec["f32"]["kernel_hash"] = "0" * 16
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    assert bench.measured_traffic("f32") is None
+
+
+def _counter_csv(path, counter, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for i, (kernel, value) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Kernel_Name": kernel, "Counter_Name": counter, "Counter_Value": value})
+
+
+def test_ingest_counters_calibrates_by_the_copy(tmp_path, capsys):
+    copy, step2, other = "__amd_rocclr_copyBuffer", "void ltne::step2_kernel<1>(float const*, ...)", \
+        "void ltne::step_kernel<float, float, 5>(...)"
+    gib = 2 ** 30
+    # FETCH_SIZE reads half the copy's bytes (scale 2), WRITE_SIZE all of them
+    _counter_csv(tmp_path / "f.csv", "FETCH_SIZE",
+                 [(copy, gib / 2048), (copy, 3.0), (step2, 2.8e6), (step2, 2.9e6), (step2, 3.0e6), (other, 9e9)])
+    _counter_csv(tmp_path / "w.csv", "WRITE_SIZE",
+                 [(copy, gib / 1024), (step2, 5.0e6), (step2, 5.2e6), (step2, 5.1e6)])
+    out = tmp_path / "traffic.json"
+    bench.ingest_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), gib, str(out))
+    capsys.readouterr()
+    rec = json.loads(out.read_text())["f32"]
+    c = rec["counters"]
+    assert c["FETCH_SIZE"]["scale"] == pytest.approx(2.0) and c["WRITE_SIZE"]["scale"] == pytest.approx(1.0)
+    # medians of the step kernel's dispatches only (the small copy and other kernels are ignored)
+    assert c["FETCH_SIZE"]["step_bytes"] == pytest.approx(2.9e6 * 1024 * 2)
+    assert c["WRITE_SIZE"]["step_bytes"] == pytest.approx(5.1e6 * 1024)
+    assert rec["bytes_per_launch"] == pytest.approx(2.9e6 * 2048 + 5.1e6 * 1024)
+    assert rec["algorithmic_bytes_per_launch"] == 156 * 8192 * 8192 * 2
+    assert rec["kernel_hash"] == bench.kernel_hash()
+
+
+def test_ingest_counters_needs_both_kernels(tmp_path):
+    _counter_csv(tmp_path / "f.csv", "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 2 ** 19)])
+    _counter_csv(tmp_path / "w.csv", "WRITE_SIZE", [("__amd_rocclr_copyBuffer", 2 ** 20)])
+    with pytest.raises(SystemExit):
+        bench.ingest_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 2 ** 30,
+                              str(tmp_path / "traffic.json"))
