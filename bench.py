@@ -70,10 +70,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(tag: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def _counters(tag: str, name: str):
+    """Entry `tag` of a committed counter summary (profiles/<name>.json),
+    if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", name + ".json")
     try:
         with open(path) as f:
             t = json.load(f)
@@ -82,7 +82,29 @@ def measured_traffic(tag: str):
     e = t.get(tag)
     if not e or e.get("kernel_hash") != kernel_hash():
         return None
-    return e.get("bytes_per_launch")
+    return e
+
+
+def measured_traffic(tag: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs
+    (FETCH_SIZE, WRITE_SIZE), if taken on the current kernel sources."""
+    e = _counters(tag, "traffic")
+    return e.get("bytes_per_launch") if e else None
+
+
+def measured_valu(tag: str):
+    """Wavefront vector instructions per launch (SQ_INSTS_VALU) from a
+    committed rocprofv3 counter run, if taken on the current kernel
+    sources."""
+    e = _counters(tag, "sq")
+    return e.get("valu_per_launch") if e else None
+
+
+# Vector instruction issue: each CU's four SIMDs issue one wavefront
+# instruction every four clocks each (a wave64 instruction occupies a 16-lane
+# SIMD for four clocks), i.e. one wavefront instruction per clock per CU.
+CUS, CLOCK_HZ = 256, 2.4e9
+VALU_ISSUE_PER_S = CUS * CLOCK_HZ
 
 
 # Forms whose steps run two to a launch (all but the last step of a call)
@@ -130,8 +152,10 @@ def time_form(tag: str, steps: int, warmup: int, inputs):
     cells = p["nx"] * p["ny"]
     ms_step = ms / steps
     mlups = cells * steps / (ms * 1e-3) / 1e6
-    # algorithmic bytes of the node updates one launch of the dominant kernel performs
-    bytes_launch = BYTES_PER_LUP[tag] * cells * steps_per_launch
+    # HBM bytes one launch must move: every population read and written once
+    # and the porosity read once per node, whether the launch advances one
+    # step or two (the intermediate level of a two-step launch stays on chip)
+    bytes_launch = BYTES_PER_LUP[tag] * cells
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
     return dict(ms_per_step=ms_step, mlups=mlups, achieved_gbs=achieved,
                 frac=achieved / HBM_PEAK_GBS, bytes_per_launch=bytes_launch, launch_ms=launch_ms,
@@ -171,10 +195,13 @@ def time_batch(steps: int, warmup: int, autotune: bool = True):
     bt.close()
     nodes = info["nodes"]
     ms_step = ms / steps
-    achieved = 152 * nodes / (ms_step * 1e-3) / 1e9
+    # one read and one write of the state (19 binary32 populations, uniform
+    # porosity) per two-step launch: 152 B per node per two steps
+    achieved = 152 * nodes / (2 * ms_step * 1e-3) / 1e9
     return dict(ms_per_step=ms_step, mlups=nodes * steps / (ms * 1e-3) / 1e6, achieved_gbs=achieved,
                 frac=achieved / HBM_PEAK_GBS, nodes=nodes, lattices=len(ps), grid=info["grid"],
                 mode="launches over all lattices, two steps per launch but the last of a call",
+                bytes_note="152 B per node per launch of two steps (state read and written once)",
                 persistent_ms_per_step=ms_persistent,
                 autotune_ms=tuned_ms)
 
@@ -205,6 +232,8 @@ def time_adjoint(n_side: int = 512, steps: int = 4000, ckpt: int = 200):
     t = time.perf_counter()
     loss, gp, gh = lat.adjoint(steps, ckpt)
     t_adj = time.perf_counter() - t
+    fwd.close()
+    lat.close()
     if loss != nu or not (np.isfinite(gp).all() and np.isfinite(gh).all()):
         raise RuntimeError("adjoint run inconsistent with the forward")
     return {"workload": ADJ_WORKLOAD, "forward_ms": round(t_fwd * 1e3, 2), "adjoint_ms": round(t_adj * 1e3, 2),
@@ -274,12 +303,52 @@ def ingest_counters(fetch_csv: str, write_csv: str, copy_bytes: int, out_path: s
     print(json.dumps(rec, indent=1))
 
 
-def cpu_baseline(inputs, budget_s: float = 12.0):
-    """The FP64 oracle on a periodic strip of the same layer: all 8192 rows,
-    512 columns, timed over as many steps as fit the budget."""
+def ingest_sq(csv_path: str, out_path: str):
+    """Turns a rocprofv3 --pmc run with SQ_INSTS_VALU (and SQ_WAVES) of
+    `bench.py --forms f32` into wavefront vector instructions per launch of
+    the FP32 two-step kernel (median over its dispatches)."""
+    import csv
+    vals = {}
+    for row in csv.DictReader(open(csv_path)):
+        k = row["Kernel_Name"]
+        if "step2_kernel" in k and ("<1>" in k or "ILi1E" in k):
+            vals.setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
+    if "SQ_INSTS_VALU" not in vals:
+        raise SystemExit("SQ_INSTS_VALU of the two-step kernel not found in %s" % csv_path)
+    rec = {"f32": {"kernel_hash": kernel_hash(), "valu_per_launch": float(np.median(vals["SQ_INSTS_VALU"])),
+                   "counters": {k: float(np.median(v)) for k, v in vals.items()},
+                   "dispatches": len(vals["SQ_INSTS_VALU"])}}
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def cpu_model() -> str:
+    """CPU model name of the host (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_STRIP_COLS = 512
+
+
+def _oracle_strip_rate(inputs, budget_s: float):
     import oracle as O
     p, phi, Tf0, Ts0 = inputs
-    cols = np.arange(512)
+    cols = np.arange(_STRIP_COLS)
     ps = dict(p, nx=len(cols), L=p["ny"] - 1.0)
     o = O.Oracle(ps, phi=phi[:, cols], Tf0=Tf0[:, cols], Ts0=Ts0[:, cols])
     t = time.perf_counter()
@@ -289,11 +358,111 @@ def cpu_baseline(inputs, budget_s: float = 12.0):
     t = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t
-    cells = ps["nx"] * ps["ny"]
-    return {"value": cells * steps / dt / 1e6, "unit": "MLUPS", "cores": O.threads(),
+    return ps["nx"] * ps["ny"] * steps / dt / 1e6, steps, dt, O.threads()
+
+
+def _single_thread_rate(budget_s: float):
+    """The oracle on the same strip with one OpenMP thread, in a child
+    process (the thread count is fixed when the oracle library loads)."""
+    import subprocess
+    code = ("import sys, json; sys.path.insert(0, %r); import bench; from paper_1608_04118_amd import inputs as I; "
+            "r = bench._oracle_strip_rate(I.throughput(n=%d, precision=I.FP32), %r); print(json.dumps(r))"
+            % (ROOT, N, budget_s))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                             timeout=10 * budget_s + 120)
+        rate, steps, dt, threads = json.loads(out.stdout.strip().splitlines()[-1])
+        return {"value": rate, "threads": threads, "steps": steps, "seconds": round(dt, 2)}
+    except Exception as e:  # reported, never fatal for the benchmark
+        return {"error": str(e)[:200]}
+
+
+def cpu_baseline(inputs, budget_s: float = 12.0):
+    """The FP64 oracle on a periodic strip of the same layer: all 8192 rows,
+    512 columns, timed over as many steps as fit the budget, on all host
+    threads and (a shorter sample) on one."""
+    rate, steps, dt, threads = _oracle_strip_rate(inputs, budget_s)
+    return {"value": rate, "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": "FP64 oracle, 8192 rows x 512 columns strip of the same layer, %d steps, "
-                      "%.1f s" % (steps, dt)}
+                      "%.1f s" % (steps, dt),
+            "cpu_model": cpu_model(), "logical_cpus": os.cpu_count(),
+            "single_thread": _single_thread_rate(budget_s / 3)}
+
+
+EXTRA_WORKLOADS = {
+    "cavity64_fp64": ("64x64 cavity, FP64 (phi 0.6, Da 1e-2, Ra 1e4)", lambda I: (I.cavity_small(), 2000)),
+    "cavity1024_fp32": ("1024x1024 cavity, FP32 (phi 0.4, Da 1e-4, Ra 1e6, gamma_sf 10, H_v 100)",
+                        lambda I: (I.cavity_large(), 2000)),
+    "channel1024x256_fp32": ("1024x256 Brinkman-Forchheimer channel, FP32 (Da 1e-4, Re 10)",
+                             lambda I: (I.channel(), 2000)),
+}
+
+
+def time_extras():
+    """Rates of the smaller workloads: the 64^2 FP64 cavity (launch-bound),
+    the 1024^2 FP32 cavity (its 159 MB of populations fit in the MI355X's
+    256 MB last-level cache) and the 1024 x 256 FP32 channel; one call of
+    the stated steps after a warm-up call, HIP events on the library's
+    stream."""
+    import torch
+    from paper_1608_04118_amd import binding as B
+    from paper_1608_04118_amd import inputs as I
+    out = {}
+    for key, (desc, make) in EXTRA_WORKLOADS.items():
+        p, steps = make(I)
+        lat = B.Lattice(p)
+        lat.step(100)
+        ms = _events_ms(lat.stream, lambda: lat.step(steps))
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+        nodes = p["nx"] * p["ny"]
+        out[key] = {"workload": desc, "steps": steps, "us_per_step": round(ms * 1e3 / steps, 3),
+                    "mlups": round(nodes * steps / (ms * 1e-3) / 1e6, 1)}
+    return out
+
+
+def roofline(head: str, r: dict, traffic):
+    """Roofline of the dominant kernel.  achieved = the HBM bytes one launch
+    must move (per node: every population read once and written once in the
+    storage type, the porosity read once -- BYTES_PER_LUP; a two-step launch
+    moves these once for its two steps) over the launch time measured live.
+    The two-step kernel is also put against its vector-instruction issue
+    (SQ_INSTS_VALU per launch from the committed counter run), the resource
+    that binds it, and its bytes are restated as if every step went to HBM
+    (one_step_equivalent: what the same node updates would cost one step per
+    launch)."""
+    nodes = N * N
+    launch_s = r["launch_ms"] * 1e-3
+    must = BYTES_PER_LUP[head] * nodes
+    achieved = must / launch_s / 1e9
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "traffic_gbs": (round(traffic / launch_s / 1e9, 1) if traffic else None),
+           "traffic_frac": (round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None),
+           "bytes_per_launch": must, "launch_ms": round(r["launch_ms"], 4)}
+    if r["steps_per_launch"] == 2:
+        eq = must * 2 / launch_s / 1e9
+        out["kernel"] = ("step2_kernel<kPhiField>: two time steps per launch over %d^2 nodes; %d B per node "
+                         "per launch (state read and written once)" % (N, BYTES_PER_LUP[head]))
+        out["one_step_equivalent"] = {"bytes_per_launch": must * 2, "gbs": round(eq, 1),
+                                      "frac": round(eq / HBM_PEAK_GBS, 4)}
+        valu = measured_valu(head)
+        if valu:
+            floor_ms = valu / VALU_ISSUE_PER_S * 1e3
+            out["valu_issue"] = {"wave_instructions_per_launch": valu,
+                                 "per_node_update": round(valu * 64 / (2 * nodes), 1),
+                                 "issue_floor_ms": round(floor_ms, 4),
+                                 "frac": round(floor_ms / r["launch_ms"], 4),
+                                 "peak": "one wavefront instruction per clock per CU, 256 CUs, 2.4 GHz"}
+        else:
+            out["valu_issue"] = None
+    else:
+        out["kernel"] = "step_kernel: one time step per launch over %d^2 nodes, %d B per node" % (
+            N, BYTES_PER_LUP[head])
+    return out
 
 
 def main():
@@ -307,14 +476,22 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the adjoint cost measurement (one JSON object)")
-    ap.add_argument("--copy-check", action="store_true",
-                    help="also time a plain 1 GiB device copy (reference for the byte counters)")
+    ap.add_argument("--no-copy-check", action="store_true",
+                    help="skip the plain 1 GiB device copy (bandwidth reference and counter calibration)")
+    ap.add_argument("--copy-check", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the small-workload rates (64^2 FP64 cavity, 1024^2 FP32 cavity, 1024x256 channel)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="convert rocprofv3 FETCH_SIZE / WRITE_SIZE runs into profiles/traffic.json")
+    ap.add_argument("--ingest-sq", metavar="SQ_CSV",
+                    help="convert a rocprofv3 SQ_INSTS_VALU run into profiles/sq.json")
     args = ap.parse_args()
     if args.ingest_counters:
         ingest_counters(args.ingest_counters[0], args.ingest_counters[1], 2 ** 30,
                         os.path.join(ROOT, "profiles", "traffic.json"))
+        return
+    if args.ingest_sq:
+        ingest_sq(args.ingest_sq, os.path.join(ROOT, "profiles", "sq.json"))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -353,9 +530,13 @@ def main():
         print("[bench] adjoint: %.1f ms vs forward %.1f ms, cost ratio %.2f" % (
             adjoint["adjoint_ms"], adjoint["forward_ms"], adjoint["cost_ratio"]), file=sys.stderr, flush=True)
     copy = None
-    if args.copy_check:
+    if not args.no_copy_check:
         print("[bench] timing a plain 1 GiB device copy", file=sys.stderr, flush=True)
         copy = copy_bandwidth()
+    extras = None
+    if not args.no_extras:
+        print("[bench] timing the small workloads", file=sys.stderr, flush=True)
+        extras = time_extras()
     head = "f32" if "f32" in res else forms[0]
     r = res[head]
     traffic = measured_traffic(head)
@@ -378,22 +559,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD + ", %s form" % head, "nx": N, "ny": N,
                    "nodes": N * N, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["frac"], 4),
-                     "traffic": traffic,
-                     "kernel": ("step2_kernel: two time steps per launch, %d B per node update x 2 x %d^2 "
-                                "nodes per launch, %.3f ms per launch" % (BYTES_PER_LUP[head], N, r["launch_ms"])
-                                if r["steps_per_launch"] == 2 else
-                                "step_kernel: %d B per node update x %d^2 nodes per launch" % (BYTES_PER_LUP[head], N)),
-                     "traffic_gbs": (round(traffic / (r["launch_ms"] * 1e-3) / 1e9, 1) if traffic else None),
-                     "note": ("achieved counts the bytes the node updates of a launch would move one step at a "
-                              "time; the two-step kernel keeps the intermediate time level on chip, so its HBM "
-                              "traffic (traffic, counter bytes per launch; traffic_gbs, that over the launch time) "
-                              "is about half of that, and frac above 1 means the launch beats the one-step HBM "
-                              "roofline; the kernel itself is bound by instruction issue and latency"
-                              if r["steps_per_launch"] == 2 else None)},
+        "roofline": roofline(head, r, traffic),
         "cpu_baseline": cpu,
         "copy_reference": copy,
+        "extras": extras,
         "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                          for kk, vv in v.items()} for k, v in res.items()},
         "batch256_f32": batch,

@@ -46,20 +46,21 @@
 extern "C" {
 #endif
 
-#define LBM_LTNE_ABI_VERSION 2
+#define LBM_LTNE_ABI_VERSION 3
 
 /* Return codes. */
 #define LBM_OK 0
 #define LBM_EINVAL (-1)       /* invalid argument or physically invalid parameters */
 #define LBM_ENOMEM (-2)       /* device allocation failed or caller pool too small */
 #define LBM_EHIP (-3)         /* a HIP runtime call failed (message in last_error) */
-#define LBM_EDIVERGED (-4)    /* non-finite mass or energy detected */
+#define LBM_EDIVERGED (-4)    /* non-finite mass or energy detected (diagnostics, or the check of diag_every) */
 #define LBM_EUNSUPPORTED (-5) /* valid request this build does not implement */
 #define LBM_ENODEV (-6)       /* no gfx950 device is available */
 
 /* Storage / arithmetic forms. */
 #define LBM_FP64 0  /* binary64 storage and arithmetic */
-#define LBM_FP32 1  /* binary32 storage and arithmetic, shifted populations */
+#define LBM_FP32 1  /* binary32 storage of shifted populations; binary32 flow arithmetic, binary64 temperature
+                       arithmetic with stochastic rounding of the temperature populations on store */
 #define LBM_FP16S 2 /* binary16 storage of shifted, power-of-two scaled populations; binary32 arithmetic,
                        stochastic rounding on store */
 #define LBM_FP32SR 3 /* binary32 storage of shifted populations; binary64 arithmetic, stochastic rounding
@@ -114,6 +115,10 @@ typedef struct lbm_ltne_params {
   double pore_size;        /* D_p / L; > 0: h_v of every node from the correlation of Eq. 52 with the
                               local Reynolds number |j| D_p / (rho nu_f) (Hv and an H_v field are then
                               not used); 0: h_v from Hv or the H_v field */
+  int32_t diag_every;      /* > 0: lbm_ltne_step checks every diag_every-th step (steps whose number
+                              is a multiple of it) for non-finite mass or energy (binary64 sums of the
+                              macroscopic fields of that step, on the device); the next synchronizing
+                              call then returns LBM_EDIVERGED.  0: no check.  Single lattices only. */
 } lbm_ltne_params;
 
 /* Lattice values derived from a parameter set (uniform phi and H_v). */
@@ -178,11 +183,16 @@ int lbm_ltne_create(const lbm_ltne_params *p, const double *phi_field, const dou
  * launch: pull streaming, wall reconstruction, macros, the three collisions,
  * store.  In the FP32 form, on lattices that yield at least 1024 strips of
  * 62 (periodic x) or 61 columns by 8 rows, all but the last step of a call
- * advance in pairs, two steps per launch with the intermediate time level
- * kept on chip; the result equals single steps bit for bit.  The macros of
- * the last step are kept for lbm_ltne_macros,
- * lbm_ltne_nusselt and lbm_ltne_diagnostics; the residual compares them with
- * the macros kept by the previous call. */
+ * (and the steps checked under diag_every) advance in pairs, two steps per
+ * launch with the intermediate time level kept on chip; the result equals
+ * single steps bit for bit.  The macros of the last step are kept for
+ * lbm_ltne_macros, lbm_ltne_nusselt and lbm_ltne_diagnostics; the residual
+ * compares them with the macros kept by the previous call that advanced the
+ * lattice (a call with nsteps = 0 changes nothing).  With diag_every > 0 a
+ * non-finite mass or energy at a checked step is recorded on the device and
+ * reported as LBM_EDIVERGED by lbm_ltne_macros, lbm_ltne_nusselt,
+ * lbm_ltne_diagnostics and lbm_ltne_save (which still fill their outputs)
+ * until a state is loaded. */
 int lbm_ltne_step(lbm_ltne_t h, int64_t nsteps);
 
 /* Steps taken since creation (or since the state loaded by lbm_ltne_load). */
@@ -210,7 +220,8 @@ int lbm_ltne_diagnostics(lbm_ltne_t h, double *mass, double *energy, double *res
 
 /* Checkpoint: bytes of a saved state, save to and load from a caller-owned
  * host buffer (populations, macros, step count).  load requires a handle
- * created with the same nx, ny and precision.  Synchronize. */
+ * created with the same nx, ny and precision, and clears a recorded
+ * divergence.  Synchronize. */
 size_t lbm_ltne_state_bytes(lbm_ltne_t h);
 int lbm_ltne_save(lbm_ltne_t h, void *host_buf, size_t bytes);
 int lbm_ltne_load(lbm_ltne_t h, const void *host_buf, size_t bytes);
@@ -255,8 +266,9 @@ int lbm_ltne_destroy(lbm_ltne_t h);
  * grid-wide barrier between steps (every barrier wait is bounded; a timeout
  * is reported as LBM_EHIP by the next synchronizing call).  Every lattice
  * evolves exactly as a single lattice with the same parameters would.
- *   ps: n parameter sets; phi_fields, Hv_fields: NULL, or n pointers each
- *   NULL or nx*ny doubles (copied).  The batch owns its device memory.
+ *   ps: n parameter sets (diag_every must be 0: LBM_EUNSUPPORTED otherwise);
+ *   phi_fields, Hv_fields: NULL, or n pointers each NULL or nx*ny doubles
+ *   (copied).  The batch owns its device memory.
  */
 int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params *ps, const double *const *phi_fields,
                           const double *const *Hv_fields, void *hip_stream, lbm_ltne_batch_t *out);

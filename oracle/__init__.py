@@ -70,41 +70,64 @@ _ORACLE_KEYS = [f[0] for f in _Params._fields_]
 _lib = None
 
 
+def compile_source(src_text: str, out_path: str) -> str:
+    """Compile oracle C source text (for instance a copy with a deliberately
+    planted mistake, in the tests that check the pins catch it) into a
+    shared library at out_path, with the flags of build()."""
+    src = out_path + ".c"
+    with open(src, "w") as f:
+        f.write(src_text)
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-Wall",
+           "-I", _HERE, "-o", out_path, src, "-lm"]
+    subprocess.check_call(cmd)
+    return out_path
+
+
+def load_library(path: str):
+    """A library built from (a variant of) the oracle source, configured like
+    the default one; pass it to Oracle(..., lib=...)."""
+    return _configure(C.CDLL(path))
+
+
 def _load():
     global _lib
     if _lib is None:
-        lib = C.CDLL(build())
-        d = C.c_double
-        dp = C.POINTER(C.c_double)
-        vp = C.c_void_p
-        lib.orc_params_size.restype = C.c_size_t
-        assert lib.orc_params_size() == C.sizeof(_Params), "oracle struct layout mismatch"
-        lib.orc_derive.argtypes = [C.POINTER(_Params), C.POINTER(_Derived)]
-        lib.orc_derive.restype = C.c_int
-        lib.orc_create.argtypes = [C.POINTER(_Params), vp, vp, vp, vp]
-        lib.orc_create.restype = vp
-        lib.orc_free.argtypes = [vp]
-        lib.orc_step.argtypes = [vp, C.c_int64]
-        lib.orc_steps_done.argtypes = [vp]
-        lib.orc_steps_done.restype = C.c_int64
-        lib.orc_macros.argtypes = [vp] + [vp] * 5
-        lib.orc_get_populations.argtypes = [vp, vp, vp, vp]
-        lib.orc_set_populations.argtypes = [vp, vp, vp, vp]
-        lib.orc_nusselt.argtypes = [vp, dp, dp]
-        lib.orc_nusselt.restype = C.c_int
-        lib.orc_diagnostics.argtypes = [vp, dp, dp, dp]
-        lib.orc_nusselt_field.argtypes = [C.POINTER(_Params), vp, C.c_int, dp]
-        lib.orc_nusselt_field.restype = C.c_int
-        lib.orc_feq.argtypes = [d, d, d, d, vp]
-        lib.orc_geq_fluid.argtypes = [d, d, d, d, d, vp]
-        lib.orc_geq_solid.argtypes = [d, d, vp]
-        lib.orc_forcing.argtypes = [d, d, d, d, d, d, vp]
-        lib.orc_matrices.argtypes = [vp, vp, vp, vp]
-        lib.orc_velocity.argtypes = [d] * 9 + [dp] * 4
-        lib.orc_temperatures.argtypes = [d] * 6 + [dp, dp]
-        lib.orc_threads.restype = C.c_int
-        _lib = lib
+        _lib = _configure(C.CDLL(build()))
     return _lib
+
+
+def _configure(lib):
+    """Declares the argument and result types of the oracle's entry points."""
+    d = C.c_double
+    dp = C.POINTER(C.c_double)
+    vp = C.c_void_p
+    lib.orc_params_size.restype = C.c_size_t
+    assert lib.orc_params_size() == C.sizeof(_Params), "oracle struct layout mismatch"
+    lib.orc_derive.argtypes = [C.POINTER(_Params), C.POINTER(_Derived)]
+    lib.orc_derive.restype = C.c_int
+    lib.orc_create.argtypes = [C.POINTER(_Params), vp, vp, vp, vp]
+    lib.orc_create.restype = vp
+    lib.orc_free.argtypes = [vp]
+    lib.orc_step.argtypes = [vp, C.c_int64]
+    lib.orc_steps_done.argtypes = [vp]
+    lib.orc_steps_done.restype = C.c_int64
+    lib.orc_macros.argtypes = [vp] + [vp] * 5
+    lib.orc_get_populations.argtypes = [vp, vp, vp, vp]
+    lib.orc_set_populations.argtypes = [vp, vp, vp, vp]
+    lib.orc_nusselt.argtypes = [vp, dp, dp]
+    lib.orc_nusselt.restype = C.c_int
+    lib.orc_diagnostics.argtypes = [vp, dp, dp, dp]
+    lib.orc_nusselt_field.argtypes = [C.POINTER(_Params), vp, C.c_int, dp]
+    lib.orc_nusselt_field.restype = C.c_int
+    lib.orc_feq.argtypes = [d, d, d, d, vp]
+    lib.orc_geq_fluid.argtypes = [d, d, d, d, d, vp]
+    lib.orc_geq_solid.argtypes = [d, d, vp]
+    lib.orc_forcing.argtypes = [d, d, d, d, d, d, vp]
+    lib.orc_matrices.argtypes = [vp, vp, vp, vp]
+    lib.orc_velocity.argtypes = [d] * 9 + [dp] * 4
+    lib.orc_temperatures.argtypes = [d] * 6 + [dp, dp]
+    lib.orc_threads.restype = C.c_int
+    return lib
 
 
 def _ptr(a):
@@ -157,8 +180,8 @@ def threads() -> int:
 class Oracle:
     """One lattice: state, stepping and outputs, all in binary64."""
 
-    def __init__(self, p: dict, phi=None, Hv=None, Tf0=None, Ts0=None):
-        lib = _load()
+    def __init__(self, p: dict, phi=None, Hv=None, Tf0=None, Ts0=None, lib=None):
+        lib = lib if lib is not None else _load()
         self.p = dict(p)
         self.nx, self.ny = int(p["nx"]), int(p["ny"])
         self._keep = [_field(a, self.ny, self.nx) for a in (phi, Hv, Tf0, Ts0)]

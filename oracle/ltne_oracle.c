@@ -655,6 +655,7 @@ static void one_step(orc *o) {
 
 void orc_step(orc *o, int64_t nsteps) {
   const size_t n = (size_t)o->nx * (size_t)o->ny;
+  if (nsteps <= 0) return; /* a call that advances nothing keeps the residual's reference */
   memcpy(o->prho, o->rho, n * sizeof(double));
   memcpy(o->pux, o->ux, n * sizeof(double));
   memcpy(o->puy, o->uy, n * sizeof(double));

@@ -9,8 +9,11 @@ The library is loaded on first use; if it has not been built, a call raises
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -40,7 +43,7 @@ class lbm_ltne_params(C.Structure):
         ("eta_e", C.c_double), ("eta_nu", C.c_double),
         ("rho0", C.c_double), ("T_ref", C.c_double),
         ("fp16_scale_f", C.c_double), ("fp16_scale_g", C.c_double),
-        ("pore_size", C.c_double),
+        ("pore_size", C.c_double), ("diag_every", C.c_int32),
     ]
 
 
@@ -280,6 +283,24 @@ def lbm_ltne_abi_version() -> int:
 
 # --- convenience wrapper ------------------------------------------------------
 
+# Live Lattice / Batch objects.  Their handles are released by close(), by
+# the garbage collector, or at the latest by the exit hook below, which runs
+# while the HIP runtime and torch (whose stream and memory a handle borrows)
+# are still alive.  A finalizer that only runs during interpreter teardown
+# makes no HIP call: the runtime may already be gone, and the process is
+# ending anyway.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for obj in list(_LIVE):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
 class Lattice:
     """One lattice on the current torch device and stream.
 
@@ -304,6 +325,7 @@ class Lattice:
             stream = torch.cuda.current_stream().cuda_stream
             self.stream = torch.cuda.current_stream()
         self.h = lbm_ltne_create(self.p, phi, Hv, Tf0, Ts0, stream, pool, nbytes)
+        _LIVE.add(self)
 
     def step(self, n: int = 1) -> "Lattice":
         lbm_ltne_step(self.h, n)
@@ -344,6 +366,8 @@ class Lattice:
         self._pool = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -487,6 +511,7 @@ class Batch:
             stream = torch.cuda.current_stream().cuda_stream
             self.stream = torch.cuda.current_stream()
         self.h = lbm_ltne_batch_create(self.ps, phi_fields, Hv_fields, stream)
+        _LIVE.add(self)
 
     def __len__(self):
         return len(self.ps)
@@ -542,6 +567,8 @@ class Batch:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -420,6 +420,8 @@ int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params* ps, const double* co
       std::string msg = last_error();
       return set_error(rc, "lattice %d: %s", i, msg.c_str());
     }
+    if (ps[i].diag_every != 0)
+      return set_error(LBM_EUNSUPPORTED, "lattice %d: diag_every is for single lattices only", i);
     const long long nn = static_cast<long long>(ps[i].nx) * ps[i].ny;
     if (phi_fields && phi_fields[i])
       for (long long j = 0; j < nn; ++j)

@@ -82,6 +82,26 @@ struct TileMap {
   int per_xcd;   // tiles per XCD; the grid has 8 * per_xcd workgroups
 };
 
+// Constants of the two temperature lattices in their arithmetic type T
+// (binary64 for the forms with binary32 or binary64 storage, binary32 for
+// binary16 storage), combined on the host.  Few on purpose: the node update
+// keeps them in scalar registers, two per binary64 value.
+template <typename T>
+struct ThermalK {
+  T Qf, Qs;               // heat sources (Eq. 45)
+  T hQf, hdQ;             // Qf / 2, (Qs - Qf) / 2
+  T T_ref;                // temperature shift
+  T w0, w1;               // D2Q5 weights 1 - varpi and varpi / 4
+  T theta_wall[4];        // Dirichlet wall temperatures relative to T_ref
+  T theta_init_f, theta_init_s;
+  T c1;                   // 5 varpi - 4
+  T z_a, z_e, z_nu;       // fluid rates (Eq. 39)
+  T e_a, e_e, e_nu;       // solid rates (Eq. 40)
+  T k3, k4;               // (1 - zeta_e / 2) c1 and (1 - eta_e / 2) c1: source factors
+  T tc;                   // 1 - zeta_a / 2 with the correction term of Sec. 3.2, else 0
+  T sg;                   // storage scale of the D2Q5 populations (1 unless FP16)
+};
+
 // Constants of one lattice in the arithmetic type C.  Temperatures are
 // carried relative to T_ref (theta = T - T_ref), populations relative to
 // their rest state at rho0 and T_ref, in every precision form.
@@ -116,6 +136,18 @@ struct StepConsts {
   int hv_corr;           // 1: h_v of every node from the correlation of Eq. 52
   C corr_a, corr_b;      // h_v / (rho c_p)_f = corr_a Re^0.644 with Re = corr_b |j| / rho
   C tc;                  // 1 - zeta_alpha / 2 with the correction term of Sec. 3.2, else 0
+  ThermalK<double> td;   // temperature-lattice constants, binary64
+  ThermalK<float> tf;    // the same, binary32
 };
+
+// The temperature-lattice constants in the type T.
+template <typename T, typename C>
+__host__ __device__ __forceinline__ const ThermalK<T>& thermal_k(const StepConsts<C>& k) {
+  if constexpr (std::is_same<T, double>::value) {
+    return k.td;
+  } else {
+    return k.tf;
+  }
+}
 
 }  // namespace ltne

@@ -88,6 +88,32 @@ inline TileMap make_tiles(int nx, int ny, int precision, int shift_override = 0,
 
 inline int grid_blocks(const TileMap& t) { return kXcdRemap ? kXcds * t.per_xcd : t.ntiles; }
 
+template <typename T>
+inline void fill_thermal_k(const lbm_ltne_params& p, const lbm_ltne_derived& d, ThermalK<T>* t) {
+  const double c1 = 5.0 * p.varpi - 4.0;
+  t->Qf = static_cast<T>(p.Qf);
+  t->Qs = static_cast<T>(p.Qs);
+  t->hQf = static_cast<T>(0.5 * p.Qf);
+  t->hdQ = static_cast<T>(0.5 * (p.Qs - p.Qf));
+  t->T_ref = static_cast<T>(d.T_ref);
+  t->w0 = static_cast<T>(1.0 - p.varpi);
+  t->w1 = static_cast<T>(0.25 * p.varpi);
+  for (int w = 0; w < 4; ++w) t->theta_wall[w] = static_cast<T>(p.T_wall[w] - d.T_ref);
+  t->theta_init_f = static_cast<T>(p.T_init_f - d.T_ref);
+  t->theta_init_s = static_cast<T>(p.T_init_s - d.T_ref);
+  t->c1 = static_cast<T>(c1);
+  t->z_a = static_cast<T>(d.zeta_a);
+  t->z_e = static_cast<T>(p.zeta_e);
+  t->z_nu = static_cast<T>(p.zeta_nu);
+  t->e_a = static_cast<T>(d.eta_a);
+  t->e_e = static_cast<T>(p.eta_e);
+  t->e_nu = static_cast<T>(p.eta_nu);
+  t->k3 = static_cast<T>((1.0 - 0.5 * p.zeta_e) * c1);
+  t->k4 = static_cast<T>((1.0 - 0.5 * p.eta_e) * c1);
+  t->tc = static_cast<T>(p.thermal_correction ? 1.0 - 0.5 * d.zeta_a : 0.0);
+  t->sg = static_cast<T>(d.scale_g);
+}
+
 template <typename C>
 inline void fill_step_consts(const lbm_ltne_params& p, const lbm_ltne_derived& d, StepConsts<C>* k) {
   k->nx = p.nx;
@@ -141,6 +167,8 @@ inline void fill_step_consts(const lbm_ltne_params& p, const lbm_ltne_derived& d
   k->corr_a = static_cast<C>(k->hv_corr ? 0.376 * std::pow(p.Pr, 0.37) * d.alpha_f / (Dp * Dp) : 0.0);
   k->corr_b = static_cast<C>(k->hv_corr ? Dp / d.nu_f : 0.0);
   k->tc = static_cast<C>(p.thermal_correction ? 1.0 - 0.5 * d.zeta_a : 0.0);
+  fill_thermal_k(p, d, &k->td);
+  fill_thermal_k(p, d, &k->tf);
 }
 
 inline int check_device(int* dev) {

@@ -40,6 +40,11 @@ struct lbm_ltne {
   void* hv() const { return has_hv ? base + lay.off_hv : nullptr; }
   double* partial() const { return reinterpret_cast<double*>(base + lay.off_partial); }
   double* result() const { return reinterpret_cast<double*>(base + lay.off_result); }
+  // step number of the first checked step with non-finite sums (0: none),
+  // in the result block after the sums
+  unsigned long long* diverged() const {
+    return reinterpret_cast<unsigned long long*>(base + lay.off_result + 16 * sizeof(double));
+  }
   long long n() const { return static_cast<long long>(p.nx) * p.ny; }
 };
 
@@ -192,6 +197,47 @@ void release(lbm_ltne* h) {
   delete h;
 }
 
+// Workgroups of the binary64 sums over the macros.
+int sum_blocks(const lbm_ltne* h) {
+  return static_cast<int>(std::min<long long>(kSumBlocks, (h->n() + kBlock - 1) / kBlock));
+}
+
+// Per-workgroup partial sums (mass, energy, residual terms) of the macro
+// buffer mac against prev, into the partial-sum scratch.
+void launch_sums(const lbm_ltne* h, const void* mac, const void* prev) {
+  const long long n = h->n();
+  if (compute_bytes(h->p.precision) == 8) {
+    hipLaunchKernelGGL((sums_kernel<double>), dim3(sum_blocks(h)), dim3(kBlock), 0, h->stream,
+                       static_cast<const double*>(mac), static_cast<const double*>(prev),
+                       static_cast<const double*>(h->phi()), h->p.phi, h->p.sigma, n, n, h->partial());
+  } else {
+    hipLaunchKernelGGL((sums_kernel<float>), dim3(sum_blocks(h)), dim3(kBlock), 0, h->stream,
+                       static_cast<const float*>(mac), static_cast<const float*>(prev),
+                       static_cast<const float*>(h->phi()), h->p.phi, h->p.sigma, n, n, h->partial());
+  }
+}
+
+// After a synchronizing call's work has completed: LBM_EDIVERGED if a step
+// checked under diag_every had non-finite sums, else rc.
+int check_diverged(lbm_ltne* h, int rc) {
+  if (h->p.diag_every <= 0 || rc != LBM_OK) return rc;
+  unsigned long long t = 0;
+  HIP_TRY(hipMemcpyAsync(&t, h->diverged(), sizeof(t), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (t != 0)
+    return set_error(LBM_EDIVERGED, "non-finite mass or energy at step %llu (checked every %d steps)", t,
+                     h->p.diag_every);
+  return rc;
+}
+
+// Clears the divergence record (creation, loading a state).
+hipError_t clear_diverged(lbm_ltne* h) {
+  static const unsigned long long zero = 0;
+  hipError_t e = hipMemcpyAsync(h->diverged(), &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -309,7 +355,7 @@ int lbm_ltne_create(const lbm_ltne_params* p, const double* phi_field, const dou
     // the residual of the first step call compares with the initial macros
     hipError_t e = hipMemcpyAsync(h->mac(1), h->mac(0), h->lay.mac_bytes, hipMemcpyDeviceToDevice,
                                   h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = clear_diverged(h);
     if (e != hipSuccess) rc = set_error(LBM_EHIP, "initialisation: %s", hipGetErrorString(e));
   }
   if (rc != LBM_OK) {
@@ -327,28 +373,44 @@ int lbm_ltne_step(lbm_ltne_t h, int64_t nsteps) {
   if (!h) return set_error(LBM_EINVAL, "handle is NULL");
   if (nsteps < 0) return set_error(LBM_EINVAL, "nsteps = %lld < 0", static_cast<long long>(nsteps));
   if (nsteps == 0) return LBM_OK;
-  int64_t s = 0;
   // two steps per launch where the lattice gives the two-step kernel enough
   // wavefronts to hide its latency (each wavefront runs a serial chain of
   // rows); small lattices run faster one step at a time
-  if (h->p.precision == LBM_FP32 &&
-      step2_waves(h->p.nx, h->p.ny, h->p.periodic_x, kStep2MinRows) >= LTNE_STEP2_MIN_WAVES) {
-    // pairs of steps in one launch while more than the last step (which
-    // also writes the macros) remain
-    for (; s + 2 <= nsteps - 1; s += 2) {
-      hipError_t e = launch_step2(h, h->steps + 1, h->pop(h->cur), h->pop(1 - h->cur));
+  const bool pairs = h->p.precision == LBM_FP32 &&
+                     step2_waves(h->p.nx, h->p.ny, h->p.periodic_x, kStep2MinRows) >= LTNE_STEP2_MIN_WAVES;
+  const int64_t de = h->p.diag_every;
+  auto checked = [de](int64_t t) { return de > 0 && t % de == 0; };
+  void* scratch_mac = h->mac(1 - h->mcur);  // overwritten by the call's last step
+  int64_t s = 0;
+  while (s < nsteps) {
+    const int64_t t = h->steps + 1;  // number of the next step
+    // a pair of steps in one launch while more than the last step (which
+    // also writes the macros) remains and neither step is checked
+    if (pairs && s + 2 <= nsteps - 1 && !checked(t) && !checked(t + 1)) {
+      hipError_t e = launch_step2(h, t, h->pop(h->cur), h->pop(1 - h->cur));
       if (e != hipSuccess) return set_error(LBM_EHIP, "step launch: %s", hipGetErrorString(e));
       h->cur = 1 - h->cur;
       h->steps += 2;
+      s += 2;
+      continue;
     }
-  }
-  for (; s < nsteps; ++s) {
-    const bool last = (s == nsteps - 1);
-    hipError_t e = launch_step(h, last ? 1 : 0, h->steps + 1, h->pop(h->cur), h->pop(1 - h->cur),
-                               last ? h->mac(1 - h->mcur) : nullptr, nullptr, nullptr);
+    const bool last = (s == nsteps - 1), check = checked(t);
+    hipError_t e = launch_step(h, (last || check) ? 1 : 0, t, h->pop(h->cur), h->pop(1 - h->cur),
+                               (last || check) ? scratch_mac : nullptr, nullptr, nullptr);
     if (e != hipSuccess) return set_error(LBM_EHIP, "step launch: %s", hipGetErrorString(e));
     h->cur = 1 - h->cur;
     h->steps += 1;
+    s += 1;
+    if (check) {
+      // binary64 mass and energy of this step's macros; a non-finite sum
+      // records the step on the device (read by the next synchronizing call)
+      const int blocks = sum_blocks(h);
+      launch_sums(h, scratch_mac, h->mac(h->mcur));
+      hipLaunchKernelGGL(finite_check_kernel, dim3(1), dim3(kBlock), 0, h->stream, h->partial(), blocks,
+                         h->diverged(), static_cast<unsigned long long>(t));
+      e = hipGetLastError();
+      if (e != hipSuccess) return set_error(LBM_EHIP, "divergence check: %s", hipGetErrorString(e));
+    }
   }
   h->mcur = 1 - h->mcur;
   return LBM_OK;
@@ -375,7 +437,7 @@ int lbm_ltne_macros(lbm_ltne_t h, double* rho, double* ux, double* uy, double* T
       for (long long i = 0; i < n; ++i) outs[f][i] = tmp[i];
     }
   }
-  return LBM_OK;
+  return check_diverged(h, LBM_OK);
 }
 
 int lbm_ltne_nusselt(lbm_ltne_t h, double* Nu_f, double* Nu_s) {
@@ -399,26 +461,13 @@ int lbm_ltne_nusselt(lbm_ltne_t h, double* Nu_f, double* Nu_s) {
   HIP_TRY(hipStreamSynchronize(h->stream));
   if (Nu_f) *Nu_f = r[0];
   if (Nu_s) *Nu_s = r[1];
-  return LBM_OK;
+  return check_diverged(h, LBM_OK);
 }
 
 int lbm_ltne_diagnostics(lbm_ltne_t h, double* mass, double* energy, double* residual) {
   if (!h) return set_error(LBM_EINVAL, "handle is NULL");
-  const long long n = h->n();
-  const int blocks = static_cast<int>(std::min<long long>(kSumBlocks, (n + kBlock - 1) / kBlock));
-  if (compute_bytes(h->p.precision) == 8) {
-    hipLaunchKernelGGL((sums_kernel<double>), dim3(blocks), dim3(kBlock), 0, h->stream,
-                       static_cast<const double*>(h->mac(h->mcur)),
-                       static_cast<const double*>(h->mac(1 - h->mcur)),
-                       static_cast<const double*>(h->phi()), h->p.phi, h->p.sigma, n, n,
-                       h->partial());
-  } else {
-    hipLaunchKernelGGL((sums_kernel<float>), dim3(blocks), dim3(kBlock), 0, h->stream,
-                       static_cast<const float*>(h->mac(h->mcur)),
-                       static_cast<const float*>(h->mac(1 - h->mcur)),
-                       static_cast<const float*>(h->phi()), h->p.phi, h->p.sigma, n, n,
-                       h->partial());
-  }
+  const int blocks = sum_blocks(h);
+  launch_sums(h, h->mac(h->mcur), h->mac(1 - h->mcur));
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(sums_final_kernel, dim3(1), dim3(kBlock), 0, h->stream, h->partial(), blocks,
                      h->result());
@@ -434,7 +483,7 @@ int lbm_ltne_diagnostics(lbm_ltne_t h, double* mass, double* energy, double* res
   if (!std::isfinite(s[0]) || !std::isfinite(s[1]))
     return set_error(LBM_EDIVERGED, "mass %g, energy %g after %lld steps", s[0], s[1],
                      static_cast<long long>(h->steps));
-  return LBM_OK;
+  return check_diverged(h, LBM_OK);
 }
 
 namespace {
@@ -468,7 +517,7 @@ int lbm_ltne_save(lbm_ltne_t h, void* host_buf, size_t bytes) {
   b += h->lay.mac_bytes;
   HIP_TRY(hipMemcpyAsync(b, h->mac(1), h->lay.mac_bytes, hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
-  return LBM_OK;
+  return check_diverged(h, LBM_OK);
 }
 
 int lbm_ltne_load(lbm_ltne_t h, const void* host_buf, size_t bytes) {
@@ -490,7 +539,7 @@ int lbm_ltne_load(lbm_ltne_t h, const void* host_buf, size_t bytes) {
   HIP_TRY(hipMemcpyAsync(h->mac(0), b, h->lay.mac_bytes, hipMemcpyHostToDevice, h->stream));
   b += h->lay.mac_bytes;
   HIP_TRY(hipMemcpyAsync(h->mac(1), b, h->lay.mac_bytes, hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(clear_diverged(h));
   h->cur = 0;
   h->mcur = hd.mcur;
   h->steps = hd.steps;

@@ -118,6 +118,7 @@ int derive(const lbm_ltne_params* p, double tmin, double tmax, lbm_ltne_derived*
   if (p->thermal_correction != 0 && p->thermal_correction != 1)
     return set_error(LBM_EINVAL, "thermal_correction must be 0 or 1");
   if (!(p->pore_size >= 0.0)) return set_error(LBM_EINVAL, "pore_size = %g must be >= 0", p->pore_size);
+  if (p->diag_every < 0) return set_error(LBM_EINVAL, "diag_every = %d must be >= 0", p->diag_every);
 
   d->cs2 = 1.0 / 3.0;
   d->csT2 = 0.5 * p->varpi;
@@ -227,6 +228,8 @@ int lbm_ltne_default_params(lbm_ltne_params* p) {
   p->rho0 = 1.0;
   p->T_ref = NAN;
   p->fp16_scale_f = p->fp16_scale_g = 0.0;
+  p->pore_size = 0.0;
+  p->diag_every = 0;
   return LBM_OK;
 }
 

@@ -1,7 +1,8 @@
 // Binary64 reductions over the macroscopic fields: mean wall Nusselt numbers
 // and the mass / thermal-energy / residual sums.  Every sum runs in a fixed
-// order (per-thread strided partials, then a fixed tree in LDS, then one
-// final workgroup over the per-workgroup partials), so repeated calls give
+// order (per-thread strided partials, a butterfly of cross-lane exchanges
+// within each wavefront, the wavefront sums through LDS, then one final
+// workgroup over the per-workgroup partials), so repeated calls give
 // bit-identical results.
 #pragma once
 
@@ -12,17 +13,26 @@ namespace ltne {
 // Number of double sums produced by sums_kernel.
 constexpr int kSums = 8;
 
+// Sum of v over the workgroup, in every thread afterwards: a butterfly of
+// cross-lane exchanges within each wavefront (lane distances 32, 16, ..., 1;
+// lane 0's order is fixed), then the kBlock / 64 wavefront sums of lane 0
+// through LDS in a fixed order, so repeated calls give bit-identical results.
+constexpr int kWaves = kBlock / 64;
 template <int N>
-__device__ __forceinline__ void block_reduce(double (&v)[N], double (*lds)[kBlock]) {
-  const int t = threadIdx.x;
-  for (int j = 0; j < N; ++j) lds[j][t] = v[j];
+__device__ __forceinline__ void block_reduce(double (&v)[N], double (*lds)[kWaves]) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] += __shfl_xor(v[j], off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int j = 0; j < N; ++j) lds[j][wave] = v[j];
   __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (t < s)
-      for (int j = 0; j < N; ++j) lds[j][t] += lds[j][t + s];
-    __syncthreads();
+  for (int j = 0; j < N; ++j) {
+    double t = lds[j][0];
+    for (int w = 1; w < kWaves; ++w) t += lds[j][w];
+    v[j] = t;
   }
-  for (int j = 0; j < N; ++j) v[j] = lds[j][0];
 }
 
 // Per-workgroup partial sums over nodes [0, n): mass, energy, and for the
@@ -34,7 +44,7 @@ __global__ __launch_bounds__(kBlock) void sums_kernel(const C* __restrict__ mac,
                                                       const C* __restrict__ phi_field, double phi_u,
                                                       double sigma, long long n, long long mplane,
                                                       double* __restrict__ partial) {
-  __shared__ double lds[kSums][kBlock];
+  __shared__ double lds[kSums][kWaves];
   double v[kSums] = {0, 0, 0, 0, 0, 0, 0, 0};
   const long long stride = static_cast<long long>(gridDim.x) * kBlock;
   for (long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
@@ -61,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void sums_kernel(const C* __restrict__ mac,
 // linkage: every translation unit that launches it has its own copy.
 static __global__ __launch_bounds__(kBlock) void sums_final_kernel(const double* __restrict__ partial,
                                                             int nparts, double* __restrict__ out) {
-  __shared__ double lds[kSums][kBlock];
+  __shared__ double lds[kSums][kWaves];
   double v[kSums] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < nparts; b += kBlock)
     for (int j = 0; j < kSums; ++j) v[j] += partial[b * kSums + j];
@@ -70,13 +80,30 @@ static __global__ __launch_bounds__(kBlock) void sums_final_kernel(const double*
     for (int j = 0; j < kSums; ++j) out[j] = v[j];
 }
 
+// Divergence check of a step: sums the mass and energy partials of
+// sums_kernel (one workgroup) and, if either is not finite, records the
+// step number in *flag unless an earlier step is already recorded.
+static __global__ __launch_bounds__(kBlock) void finite_check_kernel(const double* __restrict__ partial,
+                                                              int nparts,
+                                                              unsigned long long* __restrict__ flag,
+                                                              unsigned long long step) {
+  __shared__ double lds[2][kWaves];
+  double v[2] = {0, 0};
+  for (int b = threadIdx.x; b < nparts; b += kBlock) {
+    v[0] += partial[b * kSums + 0];
+    v[1] += partial[b * kSums + 1];
+  }
+  block_reduce<2>(v, lds);
+  if (threadIdx.x == 0 && !(isfinite(v[0]) && isfinite(v[1])) && *flag == 0ull) *flag = step;
+}
+
 // Mean Nusselt numbers of T_f and T_s over wall w (one workgroup):
 // out[0] = Nu_f, out[1] = Nu_s.
 template <typename C>
 __global__ __launch_bounds__(kBlock) void nusselt_kernel(const C* __restrict__ mac, int nx, int ny,
                                                          long long mplane, int w, int periodic_t,
                                                          double scale, double* __restrict__ out) {
-  __shared__ double lds[3][kBlock];
+  __shared__ double lds[3][kWaves];
   const int len = (w < 2) ? ny : nx;
   double v[3] = {0, 0, 0};
   const C* Tf = mac + 3 * mplane;

@@ -1,6 +1,6 @@
-// Two fused time steps per launch for the FP32 form (binary32 storage and
-// arithmetic).  The single-step kernel is bound by memory traffic at 395
-// vector instructions per 156 bytes; computing two steps per pass over the
+// Two fused time steps per launch for the FP32 form (binary32 storage,
+// binary32 flow and binary64 temperature arithmetic).  The single-step kernel
+// is bound by memory traffic; computing two steps per pass over the
 // populations halves the traffic per lattice-node update.
 //
 // Each wavefront owns a strip of columns and a chunk of rows and marches
@@ -89,16 +89,21 @@ struct Step2Map {
   int per_xcd;  // workgroups per XCD
 };
 
-// Put into registers: the 19 post-collision populations of one node.
+// Put into registers: the 19 post-collision populations of one node, rounded
+// to the storage type exactly as a store to memory would round them (the
+// binary64 temperature values of the FP32 form stochastically, with the
+// same random words), so the intermediate time level equals a single step's.
 template <typename C>
 struct RegPut {
   C* v;
   __device__ __forceinline__ void begin(int, int, const StepConsts<C>&) {}
-  __device__ __forceinline__ void pair(int i, C va, C, int j, C vb, C, uint32_t, half2_t&) {
-    v[i] = va;
-    v[j] = vb;
+  template <typename VA, typename VB>
+  __device__ __forceinline__ void pair(int i, VA va, VA, int j, VB vb, VB, uint32_t w, half2_t&) {
+    v[i] = to_storage<C>(va, w << 16);
+    v[j] = to_storage<C>(vb, w);
   }
-  __device__ __forceinline__ void single(int i, C val, C, uint32_t) { v[i] = val; }
+  template <typename V>
+  __device__ __forceinline__ void single(int i, V val, V, uint32_t r) { v[i] = to_storage<C>(val, r); }
 };
 
 // Pull from registers: populations already gathered for the node.
@@ -201,14 +206,14 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
     if (outlane) {
       const RegPull<float> rpull{g};
       GlobalPut<float, float, kStep2NtStore> put{dst};
-      node_update_with<float, float, F>(xo, y, rpull, put, phi_field, hv_field, nullptr, nullptr, nullptr, k,
-                                        step + 1u, nullptr);
-      if (!k.py && y == 1)
-        node_update_with<float, float, F>(xo, 0, rpull, put, phi_field, hv_field, nullptr, nullptr, nullptr, k,
+      // the node at row y, then the wall row it feeds (one call site)
+      const int nrep = (!k.py && (y == 1 || y == ny - 2)) ? 2 : 1;
+#pragma nounroll
+      for (int rep = 0; rep < nrep; ++rep) {
+        const int yy = rep == 0 ? y : (y == 1 ? 0 : ny - 1);
+        node_update_with<float, float, F>(xo, yy, rpull, put, phi_field, hv_field, nullptr, nullptr, nullptr, k,
                                           step + 1u, nullptr);
-      if (!k.py && y == ny - 2)
-        node_update_with<float, float, F>(xo, ny - 1, rpull, put, phi_field, hv_field, nullptr, nullptr, nullptr,
-                                          k, step + 1u, nullptr);
+      }
     }
 #pragma unroll
     for (int i = 0; i < kPlanes; ++i) {

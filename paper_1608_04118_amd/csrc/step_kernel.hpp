@@ -72,31 +72,57 @@ __device__ __forceinline__ void store_raw(S* __restrict__ p, S v) {
 // on a slowly changing field (where round-to-nearest would add the same
 // error at every step), they average out.  r carries the random bits in its
 // top 16 bits (the low 16 bits are ignored).
+template <typename S, typename V>
+constexpr bool kStochastic = !std::is_same<S, V>::value;
+
+// Arithmetic type of the two temperature lattices.  With binary32 storage and
+// arithmetic the flow lattice is fine (its rounding errors are damped by the
+// drag and viscosity within a few hundred steps), but the temperature
+// lattices are not: their moment sums cancel (the non-equilibrium part of
+// the D2Q5 energy moment is a small difference of populations of order
+// T - T_ref), so binary32 arithmetic and round-to-nearest stores leave
+// errors that repeat at every step on a slowly evolving temperature field and
+// add up over its diffusion time.  The FP32 form therefore carries the
+// temperature populations through binary64 arithmetic, from the binary32
+// loads to a stochastically rounded binary32 store; storage stays binary32.
 template <typename S, typename C>
-constexpr bool kStochastic = !std::is_same<S, C>::value;
+struct ThermalArith {
+  using type = typename std::conditional<std::is_same<S, float>::value, double, C>::type;
+};
+template <typename S, typename C>
+using thermal_t = typename ThermalArith<S, C>::type;
 
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
-template <bool NT = kNtStore, typename S, typename C>
-__device__ __forceinline__ void store_pop(S* __restrict__ p, C v, C scale, uint32_t r) {
+// The storage value of v in a same-or-wider-than-storage form: binary64 ->
+// binary32 rounds stochastically (29 discarded significand bits, 16 random
+// ones added at their top, then truncated; the conversion is then exact),
+// equal types pass through.
+template <typename S, typename V>
+__device__ __forceinline__ S to_storage(V v, uint32_t r) {
+  if constexpr (std::is_same<S, float>::value && std::is_same<V, double>::value) {
+    unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v)) +
+                           (static_cast<unsigned long long>(r >> 16) << 13);
+    u &= ~0x1fffffffull;
+    return static_cast<float>(__longlong_as_double(static_cast<long long>(u)));  // exact
+  } else {
+    static_assert(std::is_same<S, V>::value, "storage narrower than the value needs a rounding rule");
+    (void)r;
+    return v;
+  }
+}
+
+template <bool NT = kNtStore, typename S, typename V>
+__device__ __forceinline__ void store_pop(S* __restrict__ p, V v, V scale, uint32_t r) {
   if constexpr (std::is_same<S, _Float16>::value) {
     // binary32 -> binary16: the gfx950 stochastic-rounding convert adds the
     // top 13 bits of r to the 13 discarded significand bits
     half2_t h = __builtin_nondeterministic_value(h);
     h = __builtin_amdgcn_cvt_sr_f16_f32(h, static_cast<float>(v * scale), r, false);
     store_raw<NT>(p, h[0]);
-  } else if constexpr (std::is_same<S, float>::value && std::is_same<C, double>::value) {
-    // binary64 -> binary32: 29 discarded significand bits, 16 random ones
-    // added at their top
-    (void)scale;
-    unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v)) +
-                           (static_cast<unsigned long long>(r >> 16) << 13);
-    u &= ~0x1fffffffull;
-    store_raw<NT>(p, static_cast<float>(__longlong_as_double(static_cast<long long>(u))));  // exact
   } else {
     (void)scale;
-    (void)r;
-    store_raw<NT>(p, static_cast<S>(v));
+    store_raw<NT>(p, to_storage<S>(v, r));
   }
 }
 
@@ -105,9 +131,10 @@ __device__ __forceinline__ void store_pop(S* __restrict__ p, C v, C scale, uint3
 // through the gfx950 stochastic-rounding convert, which adds the top 13
 // bits of its random operand to the 13 discarded significand bits, into the
 // two halves of one register (h carries that register from pair to pair, so
-// no register is cleared for it).
-template <bool NT = kNtStore, typename S, typename C>
-__device__ __forceinline__ void store_pair(S* __restrict__ pa, C va, C sa, S* __restrict__ pb, C vb, C sb,
+// no register is cleared for it).  The two values may differ in type (a flow
+// and a temperature population of the FP32 form).
+template <bool NT = kNtStore, typename S, typename VA, typename VB>
+__device__ __forceinline__ void store_pair(S* __restrict__ pa, VA va, VA sa, S* __restrict__ pb, VB vb, VB sb,
                                            uint32_t w, half2_t& h) {
   if constexpr (std::is_same<S, _Float16>::value) {
     h = __builtin_amdgcn_cvt_sr_f16_f32(h, static_cast<float>(va * sa), w << 16, false);
@@ -131,6 +158,20 @@ __device__ __forceinline__ C dev_rcp(C v) {
     return 1.0 / v;
   } else {
     return __builtin_amdgcn_rcpf(v);
+  }
+}
+
+// Reciprocal in the temperature arithmetic: exact in binary64 forms; in
+// the FP32 form (binary64 temperatures, binary32 elsewhere) the binary32
+// hardware reciprocal refined by one Newton step (relative error ~1e-14,
+// far below the binary32 storage of the result).
+template <typename C, typename T>
+__device__ __forceinline__ T thermal_rcp(T v) {
+  if constexpr (std::is_same<T, double>::value && std::is_same<C, float>::value) {
+    double r = static_cast<double>(__builtin_amdgcn_rcpf(static_cast<float>(v)));
+    return r + r * (1.0 - v * r);
+  } else {
+    return dev_rcp(v);
   }
 }
 
@@ -227,10 +268,12 @@ struct GlobalPut {
     P = k.qs;
     x = x_;
   }
-  __device__ __forceinline__ void pair(int i, C va, C sa, int j, C vb, C sb, uint32_t w, half2_t& h) {
+  template <typename VA, typename VB>
+  __device__ __forceinline__ void pair(int i, VA va, VA sa, int j, VB vb, VB sb, uint32_t w, half2_t& h) {
     store_pair<NT>(at(drow + i * P, x), va, sa, at(drow + j * P, x), vb, sb, w, h);
   }
-  __device__ __forceinline__ void single(int i, C v, C s, uint32_t r) { store_pop<NT>(at(drow + i * P, x), v, s, r); }
+  template <typename V>
+  __device__ __forceinline__ void single(int i, V v, V s, uint32_t r) { store_pop<NT>(at(drow + i * P, x), v, s, r); }
 };
 
 template <typename S, typename C, int F, class Pull, class Put>
@@ -274,24 +317,27 @@ __device__ __forceinline__ void node_update_with(
   const C phi_c = (F & kPhiField) ? phi_field[ic] : k.phi_u;
   const C hv_c = (F & kHvField) ? hv_field[ic] : k.hv_u;
 
+  // T: arithmetic type of the temperature lattices (see ThermalArith)
+  using T = thermal_t<S, C>;
+  const ThermalK<T>& kt = thermal_k<T>(k);
   C f0, f1, f2, f3, f4, f5, f6, f7, f8;
-  C a0, a1, a2, a3, a4;  // fluid temperature populations
-  C b0, b1, b2, b3, b4;  // solid minus fluid temperature populations
+  T a0, a1, a2, a3, a4;  // fluid temperature populations
+  T b0, b1, b2, b3, b4;  // solid minus fluid temperature populations
   if constexpr ((F & kInit) != 0) {
     // t = 0: fluid at rest at rho0 (all shifted D2Q9 populations vanish) and
     // g = w~ (T - Sr / 2), so that Eqs. 43-44 give back the initial T.
-    const C thf = init_tf ? init_tf[ic] : k.theta_init_f;
-    const C ths = init_ts ? init_ts[ic] : k.theta_init_s;
+    const T thf = init_tf ? T(init_tf[ic]) : kt.theta_init_f;
+    const T ths = init_ts ? T(init_ts[ic]) : kt.theta_init_s;
     const C hv = k.hv_corr ? C(0) : hv_c * k.hvf;  // the correlation gives 0 at rest
     const C rpp = dev_rcp(phi_c * (C(1) - phi_c));  // as in the step below
-    const C d0 = C(0.5) * hv * ((C(1) - phi_c) * rpp);
-    const C d1 = C(0.5) * hv * k.inv_sigma * (phi_c * rpp);
-    const C srf = C(2) * d0 * (ths - thf) + k.Qf;
-    const C srs = C(2) * d1 * (thf - ths) + k.Qs;
-    const C w0 = C(1) - k.varpi, w1 = C(0.25) * k.varpi;
+    const T d0 = T(C(0.5) * hv * ((C(1) - phi_c) * rpp));
+    const T d1 = T(C(0.5) * hv * k.inv_sigma * (phi_c * rpp));
+    const T srf = T(2) * d0 * (ths - thf) + kt.Qf;
+    const T srs = T(2) * d1 * (thf - ths) + kt.Qs;
+    const T w0 = kt.w0, w1 = kt.w1;
     f0 = f1 = f2 = f3 = f4 = f5 = f6 = f7 = f8 = C(0);
-    const C gf = thf - C(0.5) * srf;
-    const C gh = (ths - thf) - C(0.5) * (srs - srf);
+    const T gf = thf - T(0.5) * srf;
+    const T gh = (ths - thf) - T(0.5) * (srs - srf);
     a0 = w0 * gf;
     a1 = a2 = a3 = a4 = w1 * gf;
     b0 = w0 * gh;
@@ -331,14 +377,14 @@ __device__ __forceinline__ void node_update_with(
   // fraction of the rate of multiplies)
   const C rpp = dev_rcp(phi_c * (C(1) - phi_c));
   const C rphi_c = (C(1) - phi_c) * rpp;
-  C d0 = C(0.5) * hv * rphi_c;
-  C d1 = C(0.5) * hv * k.inv_sigma * (phi_c * rpp);
-  const C sgf = ((a0 + a1) + (a2 + a3)) + a4;
-  const C sgh = ((b0 + b1) + (b2 + b3)) + b4;  // sum g_s - sum g_f
-  const C A = sgf + C(0.5) * k.Qf;
-  C D = (sgh + C(0.5) * (k.Qs - k.Qf)) * dev_rcp(C(1) + d0 + d1);
-  C thf = A + d0 * D;
-  C ths = thf + D;
+  T d0 = T(C(0.5) * hv * rphi_c);
+  T d1 = T(C(0.5) * hv * k.inv_sigma * (phi_c * rpp));
+  const T sgf = ((a0 + a1) + (a2 + a3)) + a4;
+  const T sgh = ((b0 + b1) + (b2 + b3)) + b4;  // sum g_s - sum g_f
+  const T A = sgf + kt.hQf;
+  T D = (sgh + kt.hdQ) * thermal_rcp<C>(T(1) + d0 + d1);
+  T thf = A + d0 * D;
+  T ths = thf + D;
 
   if constexpr ((F & kRecord) != 0) {
     if (!wall) {
@@ -346,14 +392,14 @@ __device__ __forceinline__ void node_update_with(
       rec[0 * k.mplane + ir] = drho;
       rec[1 * k.mplane + ir] = jx;
       rec[2 * k.mplane + ir] = jy;
-      rec[3 * k.mplane + ir] = sgf;
-      rec[4 * k.mplane + ir] = sgh;
+      rec[3 * k.mplane + ir] = C(sgf);
+      rec[4 * k.mplane + ir] = C(sgh);
     }
   }
 
   // Buoyancy (Eq. 6, gravity along -y) plus body acceleration.
   const C Gx = k.Gbx;
-  C Gy = k.Gby + k.gbeta * (thf + k.dT0);
+  C Gy = k.Gby + k.gbeta * (C(thf) + k.dT0);
 
   // Velocity, Eqs. 20-22, and total force, Eq. 5 (rFx = rho F_x).
   C ux, uy, rFx, rFy;
@@ -378,10 +424,10 @@ __device__ __forceinline__ void node_update_with(
   // the zeroth thermal moments gain the source: n_0* = n_0 + Sr (for the
   // difference lattice: Sr_s - Sr_f = Q_s - Q_f - 2 (d0 + d1) D).
   C ms3 = jx + rFx, ms5 = jy + rFy;
-  C srf = C(2) * d0 * D + k.Qf;  // Eq. 42
-  C srs = C(-2) * d1 * D + k.Qs;
-  C dsr = (k.Qs - k.Qf) - C(2) * (d0 + d1) * D;  // Sr_s - Sr_f
-  C nf0 = sgf + srf, nh0 = sgh + dsr;
+  T srf = T(2) * d0 * D + kt.Qf;  // Eq. 42
+  T srs = T(-2) * d1 * D + kt.Qs;
+  T dsr = srs - srf;  // Sr_s - Sr_f
+  T nf0 = sgf + srf, nh0 = sgh + dsr;
 
   C phi = phi_c;
   C rphi = rphi_c;
@@ -390,22 +436,22 @@ __device__ __forceinline__ void node_update_with(
     //   f(x_b) = f^eq(rho, 0) + f(x_f) - f^eq(rho, u),
     //   g_f(x_b) = g_f^eq(T_b, 0) + g_f(x_f) - g_f^eq(T_f, u), g_s likewise
     // (the difference lattice takes the difference of the two).
-    C thfb = thf, thsb = ths;
+    T thfb = thf, thsb = ths;
     int kind = 1;
     {
-      C tw = C(0);
+      T tw = T(0);
       if (wx) {
         const int w = (x == 0) ? 0 : 1;
-        if (k.wall_kind[w] == 0) { kind = 0; tw = k.theta_wall[w]; }
+        if (k.wall_kind[w] == 0) { kind = 0; tw = kt.theta_wall[w]; }
       }
       if (kind != 0 && wy) {
         const int w = (y == 0) ? 2 : 3;
-        if (k.wall_kind[w] == 0) { kind = 0; tw = k.theta_wall[w]; }
+        if (k.wall_kind[w] == 0) { kind = 0; tw = kt.theta_wall[w]; }
       }
       if (kind == 0) thfb = thsb = tw;
     }
     // T_s - T_f at the wall: zero on a Dirichlet wall, D of x_f otherwise
-    const C Db = (kind == 0) ? C(0) : D;
+    const T Db = (kind == 0) ? T(0) : D;
     const C ip = rphi_c;
     const C uu = (ux * ux + uy * uy) * ip;
     const C r9 = rho * (C(1) / C(9)), r36 = rho * (C(1) / C(36));
@@ -421,19 +467,20 @@ __device__ __forceinline__ void node_update_with(
     f7 -= r36 * (-C(3) * sp + C(4.5) * sp * sp * ip - q0);
     f8 -= r36 * (C(3) * sm + C(4.5) * sm * sm * ip - q0);
     f6 -= r36 * (-C(3) * sm + C(4.5) * sm * sm * ip - q0);
-    const C w0 = C(1) - k.varpi, w1 = C(0.25) * k.varpi;
-    const C dtf = thfb - thf, dD = Db - D;
-    const C adv = C(0.5) * (thf + k.T_ref) * ip;  // (e.u) T_f / (2 phi)
+    const T w0 = kt.w0, w1 = kt.w1;
+    const T dtf = thfb - thf, dD = Db - D;
+    const T adv = T(0.5) * (thf + kt.T_ref) * T(ip);  // (e.u) T_f / (2 phi)
+    const T tux = T(ux), tuy = T(uy);
     a0 += w0 * dtf;
-    a1 += w1 * dtf - adv * ux;
-    a3 += w1 * dtf + adv * ux;
-    a2 += w1 * dtf - adv * uy;
-    a4 += w1 * dtf + adv * uy;
+    a1 += w1 * dtf - adv * tux;
+    a3 += w1 * dtf + adv * tux;
+    a2 += w1 * dtf - adv * tuy;
+    a4 += w1 * dtf + adv * tuy;
     b0 += w0 * dD;
-    b1 += w1 * dD + adv * ux;
-    b3 += w1 * dD - adv * ux;
-    b2 += w1 * dD + adv * uy;
-    b4 += w1 * dD - adv * uy;
+    b1 += w1 * dD + adv * tux;
+    b3 += w1 * dD - adv * tux;
+    b2 += w1 * dD + adv * tuy;
+    b4 += w1 * dD - adv * tuy;
     // Prescribed wall values; coefficients at the wall node itself.
     const int ib = y * nx + x;
     phi = (F & kPhiField) ? phi_field[ib] : k.phi_u;
@@ -441,23 +488,23 @@ __device__ __forceinline__ void node_update_with(
     rphi = (C(1) - phi) * rppb;
     // (u = 0 at the wall: the correlation gives h_v = 0 there)
     const C hvb = k.hv_corr ? C(0) : ((F & kHvField) ? hv_field[ib] : k.hv_u) * k.hvf;
-    d0 = C(0.5) * hvb * rphi;
-    d1 = C(0.5) * hvb * k.inv_sigma * (phi * rppb);
+    d0 = T(C(0.5) * hvb * rphi);
+    d1 = T(C(0.5) * hvb * k.inv_sigma * (phi * rppb));
     thf = thfb;
     ths = thsb;
     D = Db;
-    Gy = k.Gby + k.gbeta * (thf + k.dT0);
+    Gy = k.Gby + k.gbeta * (C(thf) + k.dT0);
     ux = C(0);
     uy = C(0);
     rFx = rho * phi * Gx;
     rFy = rho * phi * Gy;
     ms3 = C(0.5) * rFx;  // rho u + rho F / 2 with u = 0
     ms5 = C(0.5) * rFy;
-    srf = C(2) * d0 * D + k.Qf;
-    srs = C(-2) * d1 * D + k.Qs;
-    dsr = (k.Qs - k.Qf) - C(2) * (d0 + d1) * D;
-    nf0 = thf + C(0.5) * srf;  // n_0* = T + Sr / 2 (Eq. 41 at the wall)
-    nh0 = D + C(0.5) * dsr;
+    srf = T(2) * d0 * D + kt.Qf;
+    srs = T(-2) * d1 * D + kt.Qs;
+    dsr = srs - srf;
+    nf0 = thf + T(0.5) * srf;  // n_0* = T + Sr / 2 (Eq. 41 at the wall)
+    nh0 = D + T(0.5) * dsr;
   }
 
   if constexpr ((F & kMacros) != 0) {
@@ -465,22 +512,30 @@ __device__ __forceinline__ void node_update_with(
     mac[0 * k.mplane + ib] = rho;
     mac[1 * k.mplane + ib] = ux;
     mac[2 * k.mplane + ib] = uy;
-    mac[3 * k.mplane + ib] = thf + k.T_ref;
-    mac[4 * k.mplane + ib] = ths + k.T_ref;
+    mac[3 * k.mplane + ib] = C(thf + kt.T_ref);
+    mac[4 * k.mplane + ib] = C(ths + kt.T_ref);
   }
 
   const int io = y * nx + x;  // node index (hash input)
   put.begin(x, y, k);
   // 19 x 16 random bits for the stores, two stores per word (its top and
-  // its bottom half moved to the top); unused by the same-type forms
+  // its bottom half moved to the top; population 8 takes the top half of
+  // word 4 alone); only the words of stochastically rounded stores are drawn
+  // (all ten in the narrow forms, the last five -- the ten temperature
+  // populations -- in the FP32 form)
   uint32_t rb[10];
-  if constexpr (kStochastic<S, C>) {
+  if constexpr (kStochastic<S, C> || kStochastic<S, T>) {
     const uint32_t base = mix32(static_cast<uint32_t>(io) ^ mix32(step * 0x9e3779b9u + 0x632be5abu));
     // word j: one xor-shift / multiply / xor-shift round of base + j K (the
     // full two-multiply mix is kept for base; a second multiply per word cost
     // 2% of the binary16 step and adds nothing the rounding can use)
+    constexpr int j0 = kStochastic<S, C> ? 0 : 5;
 #pragma unroll
     for (int j = 0; j < 10; ++j) {
+      if (j < j0) {
+        rb[j] = 0u;
+        continue;
+      }
       uint32_t w = base + static_cast<uint32_t>(j) * 0x85ebca77u;
       w ^= w >> 16;
       w *= 0x7feb352du;
@@ -493,7 +548,6 @@ __device__ __forceinline__ void node_update_with(
   }
 
   half2_t hs = __builtin_nondeterministic_value(hs);  // binary16 store register (see store_pair)
-  C f8_out;
   // ---- D2Q9 collision in moment space (Eq. 10) ----
   {
     const C ip = rphi;
@@ -554,72 +608,67 @@ __device__ __forceinline__ void node_update_with(
     put.pair(2, o2, sf, 3, o3, sf, rb[1], hs);
     put.pair(4, o4, sf, 5, o5, sf, rb[2], hs);
     put.pair(6, o6, sf, 7, o7, sf, rb[3], hs);
-    f8_out = o8;  // stored with the first thermal population, sharing its random word
+    put.single(8, o8, sf, rb[4]);
   }
 
   // ---- D2Q5 collisions (Eqs. 32, 33) ----
+  // g* = N^{-1} n* with N^{-1} = N^T diag(1/5, 1/2, 1/2, 1/20, 1/4): with
+  // base = n0*/5 + n3*/20, the moving populations are base +- n1*/2 + n4*/4
+  // (along x) and base +- n2*/2 - n4*/4 (along y), the rest population
+  // (n0* - n3*)/5.
   {
-    const C c1 = C(5) * k.varpi - C(4);  // -4 + 5 varpi
-    const C ip = rphi;
-    const C Tf = thf + k.T_ref;
-    const C sg = k.sg;
+    const T ip = T(rphi);
+    const T Tf = thf + kt.T_ref;
+    const T sg = kt.sg;
+    const T Tfip = Tf * ip;
+    const T qx = T(ux) * Tfip, qy = T(uy) * Tfip;  // equilibrium heat flux u T_f / phi (Eq. 37)
     // correction term of Sec. 3.2 in moments: (1 - zeta_a / 2) T_f F / phi
     // added to the post-collision heat flux of the fluid lattice (tc = 0
     // when the term is off); F = rho F / rho, the node's force of Eq. 5
-    const C tcf = k.tc * Tf * ip * inv_rho;
-    const C cx = tcf * rFx, cy = tcf * rFy;
-    // fluid phase, equilibria of Eq. 37, source moments (Sr, 0, 0, c1 Sr, 0)
+    const T tcf = kt.tc * Tfip * T(inv_rho);
+    // fluid phase, equilibria of Eq. 37, source moments (Sr, 0, 0, c1 Sr, 0):
+    //   n1* = n1 - zeta_a (n1 - u_x T_f / phi) (+ correction),
+    //   n3* = n3 - zeta_e (n3 - c1 T_f) + (1 - zeta_e / 2) c1 Sr_f,
+    //   n4* = (1 - zeta_nu) n4;
+    // tx = zeta_a (n1 - u_x T_f / phi) - correction and u3 = n3 - c1 T_f are
+    // shared with the solid phase
+    const T nf1 = a1 - a3, nf2 = a2 - a4;
+    const T nf3 = T(-4) * a0 + ((a1 + a2) + (a3 + a4));
+    const T nf4 = (a1 - a2) + (a3 - a4);
+    const T tx = kt.z_a * (nf1 - qx) - tcf * T(rFx), ty = kt.z_a * (nf2 - qy) - tcf * T(rFy);
+    const T u3 = nf3 - kt.c1 * thf;
+    T f4o;  // its last population, stored with the solid lattice's first
     {
-      const C n1 = a1 - a3, n2 = a2 - a4;
-      const C n3 = C(-4) * a0 + ((a1 + a2) + (a3 + a4));
-      const C n4 = (a1 - a2) + (a3 - a4);
-      const C ns1 = (n1 - k.z_a * (n1 - ux * Tf * ip)) + cx;
-      const C ns2 = (n2 - k.z_a * (n2 - uy * Tf * ip)) + cy;
-      const C ns3 = n3 - k.z_e * (n3 - c1 * thf) + (C(1) - C(0.5) * k.z_e) * c1 * srf;
-      const C ns4 = n4 - k.z_nu * n4;
-      // g* = N^{-1} n*, N^{-1} = N^T diag(1/5, 1/2, 1/2, 1/20, 1/4)
-      const C o0 = nf0 * C(0.2);
-      const C o3 = ns3 * C(0.05);
-      const C o4 = ns4 * C(0.25);
-      const C h1 = ns1 * C(0.5), h2 = ns2 * C(0.5);
-      const C r1 = o0 + h1 + o3 + o4, r2 = o0 + h2 + o3 - o4;
-      const C r3 = o0 - h1 + o3 + o4, r4 = o0 - h2 + o3 - o4;
-      // rest population from the conserved zeroth moment (see the flow part)
-      put.pair(8, f8_out, k.sf, 9, nf0 - ((r1 + r2) + (r3 + r4)), sg,
-                 rb[4], hs);
-      put.pair(10, r1, sg, 11, r2, sg, rb[5], hs);
-      put.pair(12, r3, sg, 13, r4, sg, rb[6], hs);
+      const T ns1 = nf1 - tx, ns2 = nf2 - ty;
+      const T ns3 = (nf3 - kt.z_e * u3) + kt.k3 * srf;
+      const T ns4 = nf4 - kt.z_nu * nf4;
+      const T base = T(0.2) * nf0 + T(0.05) * ns3;
+      const T px = base + T(0.25) * ns4, py = base - T(0.25) * ns4;
+      put.pair(9, T(0.2) * (nf0 - ns3), sg, 10, px + T(0.5) * ns1, sg, rb[5], hs);
+      put.pair(11, py + T(0.5) * ns2, sg, 12, px - T(0.5) * ns1, sg, rb[6], hs);
+      f4o = py - T(0.5) * ns2;
     }
     // solid phase (Eq. 33, equilibria of Eq. 38), carried as the difference
-    // g_s - g_f: in moments, n_h* = n_s* - n_f* with n_s = n_f + n_h,
-    //   n_h1* = (1 - eta_a) n_h1 + (zeta_a - eta_a) n_f1 - zeta_a u_x T_f / phi
+    // h = g_s - g_f: in moments, n_h* = n_s* - n_f* with n_s = n_f + n_h,
+    //   n_h1* = n_h1 - eta_a (n_h1 + n_f1) + zeta_a (n_f1 - u_x T_f / phi)
     //           (minus the fluid's correction term when it is on),
-    //   n_h3* = (1 - eta_e) n_h3 + (zeta_e - eta_e)(n_f3 - c1 T_f) + c1 eta_e D
-    //           + c1 [(1 - eta_e / 2) Sr_s - (1 - zeta_e / 2) Sr_f],
-    //   n_h4* = (1 - eta_nu) n_h4 + (zeta_nu - eta_nu) n_f4,
+    //   n_h3* = n_h3 - eta_e (n_h3 + u3 - c1 D) + zeta_e u3
+    //           + (1 - eta_e / 2) c1 Sr_s - (1 - zeta_e / 2) c1 Sr_f,
+    //   n_h4* = n_h4 - eta_nu (n_h4 + n_f4) + zeta_nu n_f4,
     // every term small where the two phases are close.
     {
-      const C nf1 = a1 - a3, nf2 = a2 - a4;
-      const C nf3 = C(-4) * a0 + ((a1 + a2) + (a3 + a4));
-      const C nf4 = (a1 - a2) + (a3 - a4);
-      const C n1 = b1 - b3, n2 = b2 - b4;
-      const C n3 = C(-4) * b0 + ((b1 + b2) + (b3 + b4));
-      const C n4 = (b1 - b2) + (b3 - b4);
-      const C ns1 = ((C(1) - k.e_a) * n1 + ((k.z_a - k.e_a) * nf1 - k.z_a * ux * Tf * ip)) - cx;
-      const C ns2 = ((C(1) - k.e_a) * n2 + ((k.z_a - k.e_a) * nf2 - k.z_a * uy * Tf * ip)) - cy;
-      const C ns3 = (C(1) - k.e_e) * n3 + (k.z_e - k.e_e) * (nf3 - c1 * thf) +
-                    c1 * (k.e_e * D + ((C(1) - C(0.5) * k.e_e) * srs - (C(1) - C(0.5) * k.z_e) * srf));
-      const C ns4 = (C(1) - k.e_nu) * n4 + (k.z_nu - k.e_nu) * nf4;
-      const C o0 = nh0 * C(0.2);
-      const C o3 = ns3 * C(0.05);
-      const C o4 = ns4 * C(0.25);
-      const C h1 = ns1 * C(0.5), h2 = ns2 * C(0.5);
-      const C r1 = o0 + h1 + o3 + o4, r2 = o0 + h2 + o3 - o4;
-      const C r3 = o0 - h1 + o3 + o4, r4 = o0 - h2 + o3 - o4;
-      put.pair(14, nh0 - ((r1 + r2) + (r3 + r4)), sg, 15, r1, sg, rb[7],
-                 hs);
-      put.pair(16, r2, sg, 17, r3, sg, rb[8], hs);
-      put.single(18, r4, sg, (rb[9] << 16));
+      const T n1 = b1 - b3, n2 = b2 - b4;
+      const T n3 = T(-4) * b0 + ((b1 + b2) + (b3 + b4));
+      const T n4 = (b1 - b2) + (b3 - b4);
+      const T ns1 = (n1 - kt.e_a * (n1 + nf1)) + tx;
+      const T ns2 = (n2 - kt.e_a * (n2 + nf2)) + ty;
+      const T ns3 = ((n3 - kt.e_e * ((n3 + u3) - kt.c1 * D)) + kt.z_e * u3) + (kt.k4 * srs - kt.k3 * srf);
+      const T ns4 = (n4 - kt.e_nu * (n4 + nf4)) + kt.z_nu * nf4;
+      const T base = T(0.2) * nh0 + T(0.05) * ns3;
+      const T px = base + T(0.25) * ns4, py = base - T(0.25) * ns4;
+      put.pair(13, f4o, sg, 14, T(0.2) * (nh0 - ns3), sg, rb[7], hs);
+      put.pair(15, px + T(0.5) * ns1, sg, 16, py + T(0.5) * ns2, sg, rb[8], hs);
+      put.pair(17, px - T(0.5) * ns1, sg, 18, py - T(0.5) * ns2, sg, rb[9], hs);
     }
   }
 }

@@ -49,7 +49,7 @@ _BASE = dict(
     body_force=(0.0, 0.0),
     rho0=1.0,
     T_ref=float("nan"), fp16_scale_f=0.0, fp16_scale_g=0.0,
-    thermal_correction=0, pore_size=0.0,
+    thermal_correction=0, pore_size=0.0, diag_every=0,
     **PAPER_RATES,
 )
 

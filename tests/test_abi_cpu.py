@@ -35,7 +35,7 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 15
     for n in names:
         assert hasattr(lib, n), n
-    assert B.lbm_ltne_abi_version() == 2
+    assert B.lbm_ltne_abi_version() == 3
 
 
 def test_struct_layout_roundtrip(lib):
@@ -48,6 +48,9 @@ def test_struct_layout_roundtrip(lib):
     assert (p.varpi, p.s_e, p.s_eps, p.s_q) == (0.4, 1.1, 1.1, 1.2)
     assert (p.zeta_e, p.zeta_nu, p.eta_e, p.eta_nu, p.rho0) == (1.1, 1.1, 1.1, 1.1, 1.0)
     assert math.isnan(p.T_ref) and p.fp16_scale_f == 0.0 and p.fp16_scale_g == 0.0
+    assert p.pore_size == 0.0 and p.diag_every == 0
+    q = B.params_from_dict(I.cavity_small(diag_every=7, pore_size=0.25))
+    assert (q.diag_every, q.pore_size) == (7, 0.25)
 
 
 @pytest.mark.parametrize("mk", [I.cavity_small, I.cavity_large, lambda: I.channel(),
@@ -82,6 +85,7 @@ BAD = [
     dict(nu_wall=5), dict(wall_thermal=(0, 0, 2, 1)), dict(fp16_scale_f=3.0),
     dict(Ra=float("nan")), dict(nx=40000, ny=40000), dict(nx=32769, ny=32768),
     dict(thermal_correction=2), dict(pore_size=-0.01), dict(pore_size=float("inf")),
+    dict(diag_every=-1),
 ]
 
 

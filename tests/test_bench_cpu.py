@@ -94,3 +94,35 @@ def test_ingest_counters_needs_both_kernels(tmp_path):
     with pytest.raises(SystemExit):
         bench.ingest_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 2 ** 30,
                               str(tmp_path / "traffic.json"))
+
+
+def test_sq_ingest_and_roofline_block(tmp_path, monkeypatch):
+    """SQ_INSTS_VALU of the two-step kernel becomes instructions per launch
+    (median), valid only for the current kernel sources; the roofline block
+    divides the bytes a launch must move by its time, and restates the
+    two-step launch against vector issue and as the one-step equivalent."""
+    _copy_sources(tmp_path)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    path = tmp_path / "sq.csv"
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for v in (1.0e9, 1.2e9, 1.1e9):
+            w.writerow({"Kernel_Name": "void ltne::step2_kernel<1>(float const*, ...)",
+                        "Counter_Name": "SQ_INSTS_VALU", "Counter_Value": v})
+        w.writerow({"Kernel_Name": "void ltne::step_kernel<float, float, 5>(...)",
+                    "Counter_Name": "SQ_INSTS_VALU", "Counter_Value": 5.0})
+    bench.ingest_sq(str(path), str(tmp_path / "profiles" / "sq.json"))
+    assert bench.measured_valu("f32") == 1.1e9
+    r = {"launch_ms": 2.5, "steps_per_launch": 2}
+    out = bench.roofline("f32", r, 11.0e9)
+    n = bench.N * bench.N
+    assert out["bytes_per_launch"] == 156 * n
+    assert abs(out["achieved"] - 156 * n / 2.5e-3 / 1e9) < 0.1
+    assert abs(out["frac"] - out["achieved"] / 8000.0) < 1e-4
+    assert abs(out["one_step_equivalent"]["gbs"] - 2 * out["achieved"]) < 0.2
+    assert abs(out["valu_issue"]["issue_floor_ms"] - 1.1e9 / (256 * 2.4e9) * 1e3) < 1e-3
+    assert abs(out["traffic_gbs"] - 11.0e9 / 2.5e-3 / 1e9) < 0.1
+    single = bench.roofline("f64", {"launch_ms": 3.6, "steps_per_launch": 1}, None)
+    assert single["bytes_per_launch"] == 312 * n and "valu_issue" not in single

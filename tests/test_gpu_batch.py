@@ -98,38 +98,85 @@ def test_batch_fp64_matches_oracle(B, oracle):
             assert v <= max(1e-12, 10 * floor[k]), (i, k, v)
 
 
-def test_batch_256_cavities(B, oracle):
-    """The 256-cavity workload (sides 64..512, seeded parameters), FP32,
-    5000 steps in one persistent launch: sampled lattices equal their single
-    runs bit for bit; the small ones match the oracle (binary32 gate 1e-5 on
-    lattices whose relaxation times all exceed 0.55; nearer 1/2 the rounding
-    is amplified and the error is reported only)."""
+def _sampled_cavities(ps):
+    """Eight cavities of the 256-cavity workload spread over its size range
+    (the cavities at the 0, 1/7, ..., 7/7 quantiles of the side, 64 to 512),
+    plus the small cavity (side <= 96) whose relaxation times come nearest
+    1/2."""
+    sides = np.array([p["nx"] for p in ps])
+    order = np.argsort(sides, kind="stable")
+    picked = [int(order[int(round(k * (len(ps) - 1) / 7))]) for k in range(8)]
+    from paper_1608_04118_amd import binding
+    small = [i for i in range(len(ps)) if ps[i]["nx"] <= 96]
+    tau = lambda i: min((lambda d: (d.tau_nu, d.tau_Tf, d.tau_Ts))(binding.lbm_ltne_derive(ps[i])))
+    worst = min(small, key=tau)
+    return picked + ([worst] if worst not in picked else [])
+
+
+@pytest.fixture(scope="module")
+def batch256(B):
+    """The 256-cavity workload (sides 64..512, seeded parameters), FP32, 5000
+    steps in the launch configuration the benchmark times (one launch over
+    every lattice per pair of steps); macros of the sampled cavities."""
     ps = I.batch()
     say("256-cavity batch: nodes", sum(p["nx"] * p["ny"] for p in ps))
     bt = B.Batch(ps)
-    bt.set_mode(1)  # one persistent launch for all 5000 steps
-    info = bt.info()
-    say("info", info)
-    assert info["persistent"] == 1
+    bt.autotune(reps=2)
+    bt.set_mode(0)
     bt.step(5000)
-    rng = np.random.default_rng(0)
-    sample = sorted(set(rng.choice(len(ps), 6, replace=False).tolist()) | {0})
-    for i in sample:
-        single = B.Lattice(ps[i]).step(5000)
-        a, b = bt.macros(i), single.macros()
-        for k in FIELDS:
-            assert np.array_equal(a[k], b[k]), (i, k)
-    small = [i for i, p in enumerate(ps) if p["nx"] <= 96][:6]
-    for i in small:
-        d = B.lbm_ltne_derive(ps[i])
-        o = oracle.Oracle(ps[i]).step(5000)
-        a, b = bt.macros(i), o.macros()
-        du = np.hypot(a["ux"] - b["ux"], a["uy"] - b["uy"]).max() / np.hypot(b["ux"], b["uy"]).max()
-        errs = [du] + [np.abs(a[k] - b[k]).max() / np.abs(b[k]).max() for k in ("Tf", "Ts")]
-        tau_min = min(d.tau_nu, d.tau_Tf, d.tau_Ts)
-        say("cavity", i, "n", ps[i]["nx"], "tau_min %.4f" % tau_min, "errors", ["%.2e" % e for e in errs])
-        if tau_min > 0.55:
-            assert max(errs) < 1e-5
+    sample = _sampled_cavities(ps)
+    out = {i: bt.macros(i) for i in sample}
+    bt.close()
+    return ps, out
+
+
+SAMPLE_IDS = list(range(9))
+
+
+@pytest.mark.parametrize("k", SAMPLE_IDS, ids=["sample%d" % k for k in SAMPLE_IDS])
+def test_batch_256_cavities(B, oracle, batch256, k):
+    """Sampled cavity k of the 256-cavity batch after 5000 steps: equal bit
+    for bit to the same cavity run alone, and within 1e-5 of the FP64 oracle
+    on u, T_f and T_s (binary32 gate).  A cavity with a relaxation time
+    below 0.505 is flagged and its error only reported."""
+    ps, got = batch256
+    keys = sorted(got)
+    if k >= len(keys):
+        pytest.skip("the smallest-tau cavity is already among the eight")
+    i = keys[k]
+    p = ps[i]
+    single = B.Lattice(p).step(5000).macros()
+    for f in FIELDS:
+        assert np.array_equal(got[i][f], single[f]), (i, f)
+    d = B.lbm_ltne_derive(p)
+    tau_min = min(d.tau_nu, d.tau_Tf, d.tau_Ts)
+    o = oracle.Oracle(p).step(5000).macros()
+    a = got[i]
+    du = np.hypot(a["ux"] - o["ux"], a["uy"] - o["uy"]).max() / np.hypot(o["ux"], o["uy"]).max()
+    errs = {"u": du, "Tf": np.abs(a["Tf"] - o["Tf"]).max() / np.abs(o["Tf"]).max(),
+            "Ts": np.abs(a["Ts"] - o["Ts"]).max() / np.abs(o["Ts"]).max()}
+    flagged = tau_min < 0.505
+    say("cavity", i, "side", p["nx"], "Ra %.3g" % p["Ra"], "tau_min %.4f" % tau_min,
+        "FLAGGED (tau < 0.505)" if flagged else "", {kk: "%.2e" % v for kk, v in errs.items()})
+    if not flagged:
+        for kk, v in errs.items():
+            assert v <= 1e-5, (i, kk, v)
+
+
+def test_batch_persistent_equals_launches(B):
+    """The persistent launch (all steps of a call in one cooperative launch
+    with a grid barrier between steps) gives the per-step launches' result
+    bit for bit on the 256-cavity workload."""
+    ps = I.batch()
+    a = B.Batch(ps)
+    a.set_mode(1)
+    assert a.info()["persistent"] == 1
+    a.step(300)
+    b = B.Batch(ps).step(300)
+    for i in (0, 17, 100, 255):
+        ma, mb = a.macros(i), b.macros(i)
+        for f in FIELDS:
+            assert np.array_equal(ma[f], mb[f]), (i, f)
 
 
 def test_two_step_batch_equals_single(B):

@@ -80,29 +80,32 @@ def test_channel_steady_profile(B, Da, gate):
 
 
 def test_cavity_large_full_length(B):
-    """1024^2 cavity, Ra = 1e6, 50000 steps.  binary64 arithmetic with
-    stochastic rounding to binary32 storage stays within 1e-5 of FP64 (gated).
-    binary32 arithmetic is reported: its round-to-nearest errors repeat at
-    every step on this slowly evolving field (thermal diffusion time ~2e7
-    steps) and add up to about 1e-4 at 50000 steps."""
+    """1024^2 cavity, Ra = 1e6, 50000 steps: the FP32 form (binary32 storage,
+    binary32 flow arithmetic, binary64 temperature arithmetic with
+    stochastically rounded stores) and FP32SR (binary64 arithmetic throughout)
+    both stay within 1e-5 of FP64 on u, T_f and T_s after every 10000 steps,
+    and their hot-wall Nusselt numbers within 1e-6.  The thermal diffusion
+    time of this cavity is about 2e7 steps, so a rounding error that repeats
+    at every step would add up over the whole run."""
     p32 = I.cavity_large()
     b = B.Lattice(dict(p32, precision=I.FP64))
     forms = {"fp32": B.Lattice(p32), "fp32sr": B.Lattice(dict(p32, precision=I.FP32SR))}
+    worst = {name: 0.0 for name in forms}
     for chunk in range(5):
         b.step(10000)
         mb = b.macros()
         for name, a in forms.items():
             a.step(10000)
             e = _rel(a.macros(), mb)
+            worst[name] = max(worst[name], max(e.values()))
             say("cavity 1024^2 after %d steps: %s vs fp64" % (10000 * (chunk + 1), name),
                 {k: "%.2e" % v for k, v in e.items()})
     nb = b.nusselt()
-    e = _rel(forms["fp32sr"].macros(), mb)
-    na = forms["fp32sr"].nusselt()
-    say("Nu fp32sr", na, "fp32", forms["fp32"].nusselt(), "fp64", nb)
-    for k, v in e.items():
-        assert v <= 1e-5, (k, v)
-    assert abs(na[0] - nb[0]) <= 1e-6 * abs(nb[0])
+    for name, a in forms.items():
+        na = a.nusselt()
+        say("Nu %s" % name, na, "fp64", nb)
+        assert worst[name] <= 1e-5, (name, worst[name])
+        assert abs(na[0] - nb[0]) <= 1e-6 * abs(nb[0]), (name, na, nb)
 
 
 def test_layer_full_size_forms(B):
