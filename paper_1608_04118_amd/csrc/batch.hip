@@ -143,15 +143,28 @@ __global__ __launch_bounds__(kStep2Block) void batch2_kernel(const CavityDesc<fl
                                                         int parity, uint32_t step) {
   const int b = blockIdx.x;
   const int blk = (b & (kXcds - 1)) * per_xcd + (b >> 3);
-  const int wave = blk * (kStep2Block / 64) + (static_cast<int>(threadIdx.x) >> 6);
+  const int wl = static_cast<int>(threadIdx.x) >> 6;
+  const int wave = blk * (kStep2Block / 64) + wl;
+  // each wavefront's lattice's binary64 temperature constants in LDS (see
+  // step2_kernel), copied by its own lanes before the workgroup barrier
+  __shared__ ThermalK<double> kts[kStep2Block / 64];
+  const int c = wave < nwaves ? __builtin_amdgcn_readfirstlane(wave_cav[wave]) : 0;
+  {
+    constexpr int words = sizeof(ThermalK<double>) / 8;
+    static_assert(sizeof(ThermalK<double>) % 8 == 0 && words <= 64, "constant block too large");
+    const int lane = static_cast<int>(threadIdx.x) & 63;
+    if (wave < nwaves && lane < words)
+      reinterpret_cast<unsigned long long*>(&kts[wl])[lane] =
+          reinterpret_cast<const unsigned long long*>(&ks[c].td)[lane];
+  }
+  __syncthreads();
   if (wave >= nwaves) return;  // whole wavefronts
-  const int c = __builtin_amdgcn_readfirstlane(wave_cav[wave]);
   const StepConsts<float>& k = ks[c];
   const CavityDesc<float>& d = cav[c];
   const int local = wave - d.wave_begin;
   const int nstrips = (k.nx + step2_out(k.px) - 1) / step2_out(k.px);
   step2_wave<F>(static_cast<const float*>(d.pop[parity]), static_cast<float*>(d.pop[parity ^ 1]), d.phi, d.hv, k,
-                local % nstrips, local / nstrips, kBatch2Rows, step);
+                kts[wl], local % nstrips, local / nstrips, kBatch2Rows, step);
 }
 
 }  // namespace ltne

@@ -89,6 +89,15 @@ struct Step2Map {
   int per_xcd;  // workgroups per XCD
 };
 
+// Copies a constant block into LDS, one 8-byte word per thread.
+template <typename K>
+__device__ __forceinline__ void copy_to_lds(const K& src, K& dst) {
+  static_assert(sizeof(K) % 8 == 0 && sizeof(K) / 8 <= kStep2Block, "constant block too large");
+  const int t = static_cast<int>(threadIdx.x);
+  if (t < static_cast<int>(sizeof(K) / 8))
+    reinterpret_cast<unsigned long long*>(&dst)[t] = reinterpret_cast<const unsigned long long*>(&src)[t];
+}
+
 // Put into registers: the 19 post-collision populations of one node, rounded
 // to the storage type exactly as a store to memory would round them (the
 // binary64 temperature values of the FP32 form stochastically, with the
@@ -117,11 +126,13 @@ struct RegPull {
 };
 
 // One wavefront's strip and chunk of a lattice.
+// kt: the lattice's temperature constants, a copy in LDS (see the kernels).
 template <int F>
 __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float* __restrict__ dst,
                                            const float* __restrict__ phi_field, const float* __restrict__ hv_field,
-                                           const StepConsts<float>& k, const int strip, const int chunk,
-                                           const int rows, const uint32_t step) {
+                                           const StepConsts<float>& k, const ThermalK<double>& kt,
+                                           const int strip, const int chunk, const int rows,
+                                           const uint32_t step) {
   const int lane = static_cast<int>(threadIdx.x) & 63;
   const int nx = k.nx, ny = k.ny;
   const int halo = step2_halo(k.px), out = step2_out(k.px);
@@ -176,7 +187,7 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
       const RegPull<float> rp{v};
       RegPut<float> put{w};
       node_update_with<float, float, F>(col, r, rp, put, phi_field, hv_field, nullptr, nullptr, nullptr, k, step,
-                                        nullptr);
+                                        nullptr, kt);
     } else {
 #pragma unroll
       for (int i = 0; i < kPlanes; ++i) w[i] = 0.0f;
@@ -212,7 +223,7 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
       for (int rep = 0; rep < nrep; ++rep) {
         const int yy = rep == 0 ? y : (y == 1 ? 0 : ny - 1);
         node_update_with<float, float, F>(xo, yy, rpull, put, phi_field, hv_field, nullptr, nullptr, nullptr, k,
-                                          step + 1u, nullptr);
+                                          step + 1u, nullptr, kt);
       }
     }
 #pragma unroll
@@ -232,8 +243,13 @@ __global__ __launch_bounds__(kStep2Block) void step2_kernel(const float* __restr
   const int b = blockIdx.x;
   const int blk = (b & (kXcds - 1)) * m.per_xcd + (b >> 3);
   const int wave = blk * (kStep2Block / 64) + (static_cast<int>(threadIdx.x) >> 6);
+  // the binary64 temperature constants as vector operands from LDS rather
+  // than scalar registers (which the kernel runs short of)
+  __shared__ ThermalK<double> kt;
+  copy_to_lds(k.td, kt);
+  __syncthreads();
   if (wave >= m.nwaves) return;  // whole wavefronts
-  step2_wave<F>(src, dst, phi_field, hv_field, k, wave % m.nstrips, wave / m.nstrips, m.rows, step);
+  step2_wave<F>(src, dst, phi_field, hv_field, k, kt, wave % m.nstrips, wave / m.nstrips, m.rows, step);
 }
 
 }  // namespace ltne

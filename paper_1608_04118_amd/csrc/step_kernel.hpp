@@ -80,17 +80,26 @@ constexpr bool kStochastic = !std::is_same<S, V>::value;
 // drag and viscosity within a few hundred steps), but the temperature
 // lattices are not: their moment sums cancel (the non-equilibrium part of
 // the D2Q5 energy moment is a small difference of populations of order
-// T - T_ref), so binary32 arithmetic and round-to-nearest stores leave
-// errors that repeat at every step on a slowly evolving temperature field and
-// add up over its diffusion time.  The FP32 form therefore carries the
-// temperature populations through binary64 arithmetic, from the binary32
-// loads to a stochastically rounded binary32 store; storage stays binary32.
+// T - T_ref), and a temperature that round-to-nearest stores shift by the
+// same fraction of a unit in the last place at every step drifts over the
+// field's diffusion time (1.3e-4 after 50000 steps of the 1024^2 cavity).
+// The FP32 form therefore carries the temperature populations through
+// binary64 arithmetic, from the binary32 loads to the binary32 stores; the
+// moving populations are rounded to nearest and the rest population, which
+// closes the zeroth moment (the temperature itself) exactly in binary64
+// against the rounded moving ones, stochastically (kRestOnlySR): the stored
+// temperature is then unbiased, and the errors of the other moments relax
+// away.
 template <typename S, typename C>
 struct ThermalArith {
   using type = typename std::conditional<std::is_same<S, float>::value, double, C>::type;
 };
 template <typename S, typename C>
 using thermal_t = typename ThermalArith<S, C>::type;
+// Only the temperature lattices' rest populations round stochastically (the
+// FP32 form); the narrow forms round every stored value stochastically.
+template <typename S, typename C>
+constexpr bool kRestOnlySR = std::is_same<S, float>::value && std::is_same<C, float>::value;
 
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
@@ -276,12 +285,15 @@ struct GlobalPut {
   __device__ __forceinline__ void single(int i, V v, V s, uint32_t r) { store_pop<NT>(at(drow + i * P, x), v, s, r); }
 };
 
+// kt: the temperature-lattice constants of k (thermal_k), passed apart so a
+// caller can hand in a copy in LDS (the two-step kernel: vector operands that
+// free the scalar registers of the binary64 constants).
 template <typename S, typename C, int F, class Pull, class Put>
 __device__ __forceinline__ void node_update_with(
     const int x, const int y, const Pull& pull, Put& put,
     const C* __restrict__ phi_field, const C* __restrict__ hv_field, C* __restrict__ mac,
     const C* __restrict__ init_tf, const C* __restrict__ init_ts, const StepConsts<C>& k,
-    const uint32_t step, C* __restrict__ rec);
+    const uint32_t step, C* __restrict__ rec, const ThermalK<thermal_t<S, C>>& kt);
 
 // One node update: pull, macros, walls, collisions, store.  step numbers
 // the time step being computed (0: initialisation); with a narrow storage
@@ -294,7 +306,8 @@ __device__ __forceinline__ void node_update(
     const uint32_t step, C* __restrict__ rec = nullptr) {
   const GlobalPull<S, C> pull{src};
   GlobalPut<S, C> put{dst};
-  node_update_with<S, C, F>(x, y, pull, put, phi_field, hv_field, mac, init_tf, init_ts, k, step, rec);
+  node_update_with<S, C, F>(x, y, pull, put, phi_field, hv_field, mac, init_tf, init_ts, k, step, rec,
+                            thermal_k<thermal_t<S, C>>(k));
 }
 
 template <typename S, typename C, int F, class Pull, class Put>
@@ -302,7 +315,7 @@ __device__ __forceinline__ void node_update_with(
     const int x, const int y, const Pull& pull, Put& put,
     const C* __restrict__ phi_field, const C* __restrict__ hv_field, C* __restrict__ mac,
     const C* __restrict__ init_tf, const C* __restrict__ init_ts, const StepConsts<C>& k,
-    const uint32_t step, C* __restrict__ rec) {
+    const uint32_t step, C* __restrict__ rec, const ThermalK<thermal_t<S, C>>& kt) {
   const int nx = k.nx, ny = k.ny;
 
   // Wall classification and the node whose post-streaming populations this
@@ -319,7 +332,6 @@ __device__ __forceinline__ void node_update_with(
 
   // T: arithmetic type of the temperature lattices (see ThermalArith)
   using T = thermal_t<S, C>;
-  const ThermalK<T>& kt = thermal_k<T>(k);
   C f0, f1, f2, f3, f4, f5, f6, f7, f8;
   T a0, a1, a2, a3, a4;  // fluid temperature populations
   T b0, b1, b2, b3, b4;  // solid minus fluid temperature populations
@@ -520,22 +532,20 @@ __device__ __forceinline__ void node_update_with(
   put.begin(x, y, k);
   // 19 x 16 random bits for the stores, two stores per word (its top and
   // its bottom half moved to the top; population 8 takes the top half of
-  // word 4 alone); only the words of stochastically rounded stores are drawn
-  // (all ten in the narrow forms, the last five -- the ten temperature
-  // populations -- in the FP32 form)
+  // word 4 alone).  The FP32 form needs only the two rest populations'
+  // 16 bits each: the halves of the node's hash itself (word 5).
   uint32_t rb[10];
-  if constexpr (kStochastic<S, C> || kStochastic<S, T>) {
+  if constexpr (kRestOnlySR<S, C>) {
+#pragma unroll
+    for (int j = 0; j < 10; ++j) rb[j] = 0u;
+    rb[5] = mix32(static_cast<uint32_t>(io) ^ mix32(step * 0x9e3779b9u + 0x632be5abu));
+  } else if constexpr (kStochastic<S, C>) {
     const uint32_t base = mix32(static_cast<uint32_t>(io) ^ mix32(step * 0x9e3779b9u + 0x632be5abu));
     // word j: one xor-shift / multiply / xor-shift round of base + j K (the
     // full two-multiply mix is kept for base; a second multiply per word cost
     // 2% of the binary16 step and adds nothing the rounding can use)
-    constexpr int j0 = kStochastic<S, C> ? 0 : 5;
 #pragma unroll
     for (int j = 0; j < 10; ++j) {
-      if (j < j0) {
-        rb[j] = 0u;
-        continue;
-      }
       uint32_t w = base + static_cast<uint32_t>(j) * 0x85ebca77u;
       w ^= w >> 16;
       w *= 0x7feb352du;
@@ -638,15 +648,26 @@ __device__ __forceinline__ void node_update_with(
     const T tx = kt.z_a * (nf1 - qx) - tcf * T(rFx), ty = kt.z_a * (nf2 - qy) - tcf * T(rFy);
     const T u3 = nf3 - kt.c1 * thf;
     T f4o;  // its last population, stored with the solid lattice's first
+    S f4;   // the same, rounded (FP32 form)
     {
       const T ns1 = nf1 - tx, ns2 = nf2 - ty;
       const T ns3 = (nf3 - kt.z_e * u3) + kt.k3 * srf;
       const T ns4 = nf4 - kt.z_nu * nf4;
       const T base = T(0.2) * nf0 + T(0.05) * ns3;
       const T px = base + T(0.25) * ns4, py = base - T(0.25) * ns4;
-      put.pair(9, T(0.2) * (nf0 - ns3), sg, 10, px + T(0.5) * ns1, sg, rb[5], hs);
-      put.pair(11, py + T(0.5) * ns2, sg, 12, px - T(0.5) * ns1, sg, rb[6], hs);
-      f4o = py - T(0.5) * ns2;
+      if constexpr (kRestOnlySR<S, C>) {
+        // moving populations rounded to nearest; the rest population closes
+        // the zeroth moment against them in binary64, rounded stochastically
+        const S q1 = S(px + T(0.5) * ns1), q2 = S(py + T(0.5) * ns2), q3 = S(px - T(0.5) * ns1);
+        f4 = S(py - T(0.5) * ns2);
+        const T rest = nf0 - ((T(q1) + T(q2)) + (T(q3) + T(f4)));
+        put.pair(9, rest, sg, 10, q1, S(1), rb[5], hs);
+        put.pair(11, q2, S(1), 12, q3, S(1), 0u, hs);
+      } else {
+        put.pair(9, T(0.2) * (nf0 - ns3), sg, 10, px + T(0.5) * ns1, sg, rb[5], hs);
+        put.pair(11, py + T(0.5) * ns2, sg, 12, px - T(0.5) * ns1, sg, rb[6], hs);
+        f4o = py - T(0.5) * ns2;
+      }
     }
     // solid phase (Eq. 33, equilibria of Eq. 38), carried as the difference
     // h = g_s - g_f: in moments, n_h* = n_s* - n_f* with n_s = n_f + n_h,
@@ -666,9 +687,18 @@ __device__ __forceinline__ void node_update_with(
       const T ns4 = (n4 - kt.e_nu * (n4 + nf4)) + kt.z_nu * nf4;
       const T base = T(0.2) * nh0 + T(0.05) * ns3;
       const T px = base + T(0.25) * ns4, py = base - T(0.25) * ns4;
-      put.pair(13, f4o, sg, 14, T(0.2) * (nh0 - ns3), sg, rb[7], hs);
-      put.pair(15, px + T(0.5) * ns1, sg, 16, py + T(0.5) * ns2, sg, rb[8], hs);
-      put.pair(17, px - T(0.5) * ns1, sg, 18, py - T(0.5) * ns2, sg, rb[9], hs);
+      if constexpr (kRestOnlySR<S, C>) {
+        const S q1 = S(px + T(0.5) * ns1), q2 = S(py + T(0.5) * ns2), q3 = S(px - T(0.5) * ns1),
+                q4 = S(py - T(0.5) * ns2);
+        const T rest = nh0 - ((T(q1) + T(q2)) + (T(q3) + T(q4)));
+        put.pair(13, f4, S(1), 14, rest, sg, rb[5], hs);  // the top half of the node's word
+        put.pair(15, q1, S(1), 16, q2, S(1), 0u, hs);
+        put.pair(17, q3, S(1), 18, q4, S(1), 0u, hs);
+      } else {
+        put.pair(13, f4o, sg, 14, T(0.2) * (nh0 - ns3), sg, rb[7], hs);
+        put.pair(15, px + T(0.5) * ns1, sg, 16, py + T(0.5) * ns2, sg, rb[8], hs);
+        put.pair(17, px - T(0.5) * ns1, sg, 18, py - T(0.5) * ns2, sg, rb[9], hs);
+      }
     }
   }
 }
