@@ -295,6 +295,32 @@ int lbm_ltne_batch_get_tiles(lbm_ltne_batch_t b, int32_t *tile_shift);
 int lbm_ltne_batch_autotune(lbm_ltne_batch_t b, int32_t reps, double *ms_per_step);
 int lbm_ltne_batch_destroy(lbm_ltne_batch_t b);
 
+/*
+ * Binary64 sums of macroscopic fields held by the caller, computed without
+ * any allocation -- for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The sums are those of lbm_ltne_diagnostics, in the same fixed
+ * order (bit-identical for the same fields): total mass, thermal energy and
+ * the residual between mac and prev.
+ *   p: nx, ny; precision selects the compute type of the fields (double for
+ *     LBM_FP64 and LBM_FP32SR, float for LBM_FP32 and LBM_FP16S); phi (used
+ *     when phi_field is NULL) and sigma weight the energy.
+ *   mac, prev: device addresses of 5 planes of nx*ny values each (rho, u_x,
+ *     u_y, T_f, T_s; node (x, y) at y * nx + x), the current and the
+ *     previous macros; borrowed, read only.
+ *   phi_field: device address of nx*ny porosities in the compute type, or NULL.
+ *   hip_stream: the stream to queue on (NULL: default stream); synchronized.
+ * Scratch: a file-scope device array of about 66 KB per GPU, held until the
+ * process ends; calls that overlap on one GPU race on it.  Lattices of up
+ * to 2^30 nodes.  Errors: LBM_EINVAL (NULL field pointer, empty or oversized
+ * lattice, unknown precision, phi or sigma out of range), LBM_EHIP,
+ * LBM_EUNSUPPORTED (device index above 63), LBM_EDIVERGED (a non-finite mass
+ * or energy; the outputs are filled).
+ */
+int lbm_ltne_macro_sums_noalloc(const lbm_ltne_params *p, const void *mac, const void *prev,
+                                const void *phi_field, void *hip_stream, double *mass, double *energy,
+                                double *residual);
+
 /* Static description of a return code. */
 const char *lbm_ltne_strerror(int code);
 

@@ -111,6 +111,7 @@ def lib():
             "lbm_ltne_strerror": ([C.c_int], C.c_char_p),
             "lbm_ltne_last_error": ([], C.c_char_p),
             "lbm_ltne_abi_version": ([], C.c_int),
+            "lbm_ltne_macro_sums_noalloc": ([P, vp, vp, vp, vp, dp, dp, dp], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -267,6 +268,19 @@ def lbm_ltne_get_derived(h) -> lbm_ltne_derived:
 
 def lbm_ltne_destroy(h):
     _check(lib().lbm_ltne_destroy(h), "lbm_ltne_destroy")
+
+
+def lbm_ltne_macro_sums_noalloc(p, mac_ptr: int, prev_ptr: int, phi_ptr=None, hip_stream=None):
+    """(mass, energy, residual) of caller-held device macro fields (raw
+    addresses of 5 planes rho, u_x, u_y, T_f, T_s of nx*ny values each, in
+    the compute type of p's precision), with no device allocation."""
+    m, e, r = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().lbm_ltne_macro_sums_noalloc(C.byref(_as_params(p)), C.c_void_p(mac_ptr), C.c_void_p(prev_ptr),
+                                             C.c_void_p(phi_ptr) if phi_ptr else None,
+                                             C.c_void_p(hip_stream) if hip_stream else None,
+                                             C.byref(m), C.byref(e), C.byref(r)),
+           "lbm_ltne_macro_sums_noalloc")
+    return m.value, e.value, r.value
 
 
 def lbm_ltne_strerror(code: int) -> str:

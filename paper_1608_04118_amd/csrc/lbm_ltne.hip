@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -861,3 +862,81 @@ int lbm_ltne_destroy(lbm_ltne_t h) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Binary64 sums of caller-held macro fields without any allocation.
+//
+// The partial sums and the result live in a file-scope device array: each
+// GPU the library runs on holds one copy (about 66 KB) until the process
+// ends.  Host code never uses the array's name as an address: at the first
+// call on a device, with that device current, hipGetSymbolAddress gives the
+// device's own address, which is kept per device.
+namespace {
+constexpr int kNoAllocMaxDevices = 64;
+constexpr size_t kNoAllocScratchDoubles = static_cast<size_t>(kSumBlocks) * kSums + 32;
+__device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+int scratch_for_current_device(double** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices)
+    return set_error(LBM_EUNSUPPORTED, "device %d beyond the %d devices this entry point supports", dev,
+                     kNoAllocMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return set_error(LBM_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+}  // namespace
+
+extern "C" int lbm_ltne_macro_sums_noalloc(const lbm_ltne_params* p, const void* mac, const void* prev,
+                                           const void* phi_field, void* hip_stream, double* mass,
+                                           double* energy, double* residual) {
+  clear_error();
+  if (!p || !mac || !prev) return set_error(LBM_EINVAL, "params, mac and prev must not be NULL");
+  if (p->precision < LBM_FP64 || p->precision > LBM_FP32SR)
+    return set_error(LBM_EINVAL, "precision %d is not a precision form", p->precision);
+  if (p->nx < 1 || p->ny < 1) return set_error(LBM_EINVAL, "lattice %d x %d is empty", p->nx, p->ny);
+  const long long n = static_cast<long long>(p->nx) * p->ny;
+  if (n > (1LL << 30)) return set_error(LBM_EINVAL, "lattice %d x %d exceeds 2^30 nodes", p->nx, p->ny);
+  if (!phi_field && !(p->phi > 0.0 && p->phi < 1.0))
+    return set_error(LBM_EINVAL, "phi = %g not in (0, 1)", p->phi);
+  if (!(p->sigma > 0.0)) return set_error(LBM_EINVAL, "sigma = %g must be > 0", p->sigma);
+  double* scr = nullptr;
+  int rc = scratch_for_current_device(&scr);
+  if (rc != LBM_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  double* partial = scr;
+  double* result = scr + static_cast<size_t>(kSumBlocks) * kSums;
+  const int blocks = static_cast<int>(std::min<long long>(kSumBlocks, (n + kBlock - 1) / kBlock));
+  if (compute_bytes(p->precision) == 8) {
+    hipLaunchKernelGGL((sums_kernel<double>), dim3(blocks), dim3(kBlock), 0, st, static_cast<const double*>(mac),
+                       static_cast<const double*>(prev), static_cast<const double*>(phi_field), p->phi,
+                       p->sigma, n, n, partial);
+  } else {
+    hipLaunchKernelGGL((sums_kernel<float>), dim3(blocks), dim3(kBlock), 0, st, static_cast<const float*>(mac),
+                       static_cast<const float*>(prev), static_cast<const float*>(phi_field), p->phi,
+                       p->sigma, n, n, partial);
+  }
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(sums_final_kernel, dim3(1), dim3(kBlock), 0, st, partial, blocks, result);
+  HIP_TRY(hipGetLastError());
+  double s[kSums];
+  HIP_TRY(hipMemcpyAsync(s, result, sizeof(s), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  auto rel = [](double num, double den) { return den > 0.0 ? num / den : num; };
+  if (mass) *mass = s[0];
+  if (energy) *energy = s[1];
+  if (residual) *residual = std::max(rel(s[2], s[3]), std::max(rel(s[4], s[5]), rel(s[6], s[7])));
+  if (!std::isfinite(s[0]) || !std::isfinite(s[1]))
+    return set_error(LBM_EDIVERGED, "mass %g, energy %g", s[0], s[1]);
+  return LBM_OK;
+}

@@ -144,3 +144,20 @@ def test_null_handles_are_refused(lib):
     assert L.lbm_ltne_step(None, 1) == B.LBM_EINVAL
     assert L.lbm_ltne_adjoint(None, 10, 0, None, None, None) == B.LBM_EINVAL
     assert L.lbm_ltne_destroy(None) in (B.LBM_OK, B.LBM_EINVAL)
+
+
+def test_noalloc_sums_reject_bad_arguments_on_the_host(lib):
+    """The allocation-free sums refuse missing fields, unknown precisions and
+    oversized lattices before touching a device."""
+    import ctypes as C
+    L = B.lib()
+    p = B.params_from_dict(I.cavity_small())
+    out = [C.c_double() for _ in range(3)]
+    refs = [C.byref(o) for o in out]
+    assert L.lbm_ltne_macro_sums_noalloc(C.byref(p), None, None, None, None, *refs) == B.LBM_EINVAL
+    fake = C.c_void_p(0x1000)
+    bad = B.params_from_dict(I.cavity_small(precision=7))
+    assert L.lbm_ltne_macro_sums_noalloc(C.byref(bad), fake, fake, None, None, *refs) == B.LBM_EINVAL
+    big = B.params_from_dict(I.cavity_small(nx=40000, ny=40000))
+    assert L.lbm_ltne_macro_sums_noalloc(C.byref(big), fake, fake, None, None, *refs) == B.LBM_EINVAL
+    assert "2^30" in B.lbm_ltne_last_error()
