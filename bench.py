@@ -397,6 +397,12 @@ EXTRA_WORKLOADS = {
                         lambda I: (I.cavity_large(), 2000)),
     "channel1024x256_fp32": ("1024x256 Brinkman-Forchheimer channel, FP32 (Da 1e-4, Re 10)",
                              lambda I: (I.channel(), 2000)),
+    "paper_cavity128_fp64": ("the paper's cavity, 128x128, Ra 1e6, FP64, h_v from Eq. 52",
+                             lambda I: (I.paper_cavity(n=128, Ra=1e6), 4000)),
+    "paper_cavity192_fp64": ("the paper's cavity, 192x192, Ra 1e9, FP64, h_v from Eq. 52",
+                             lambda I: (I.paper_cavity(n=192, Ra=1e9), 4000)),
+    "adjoint_cavity512_fp32": ("512x512 cavity of the adjoint workload (Ra 1e5, Da 1e-3; uniform phi 0.65, H_v 10), FP32",
+                               lambda I: (I.adjoint_cavity(512)[0], 2000)),
 }
 
 

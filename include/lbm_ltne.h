@@ -261,7 +261,7 @@ int lbm_ltne_destroy(lbm_ltne_t h);
  * (one precision per batch) advanced together.  By default (mode 0) a batch
  * step is one launch over the combined tile list of all lattices (FP32
  * batches of at least 1024 strips of 8 rows: pairs of steps per launch, as in
- * lbm_ltne_step, with 16-row chunks); mode 1
+ * lbm_ltne_step, with per-lattice chunk heights, 16 rows by default); mode 1
  * runs all steps of a call in one persistent cooperative launch with a
  * grid-wide barrier between steps (every barrier wait is bounded; a timeout
  * is reported as LBM_EHIP by the next synchronizing call).  Every lattice
@@ -288,10 +288,17 @@ int lbm_ltne_batch_info(lbm_ltne_batch_t b, int64_t *nodes, int32_t *tiles, int3
 /* Tile width of each lattice as log2 (6, 7, 8 = 64, 128, 256 nodes wide; 0 = default). */
 int lbm_ltne_batch_set_tiles(lbm_ltne_batch_t b, const int32_t *tile_shift);
 int lbm_ltne_batch_get_tiles(lbm_ltne_batch_t b, int32_t *tile_shift);
+/* Chunk height (rows) of each lattice's wavefronts in the two-step launches
+ * of an FP32 batch: 8, 12, 16, 24 or 32 (0 = default 16). */
+int lbm_ltne_batch_set_chunks(lbm_ltne_batch_t b, const int32_t *rows);
+int lbm_ltne_batch_get_chunks(lbm_ltne_batch_t b, int32_t *rows);
 /* Autotuner: for each size class (lattices of equal nx) tries tile widths
- * 64/128/256 by timing reps batch steps from a snapshot of the state (the
- * state is restored afterwards) and keeps the fastest; ms_per_step (may be
- * NULL) receives the best time per step. */
+ * 64/128/256 by timing reps single-step launches, then (FP32 batches that
+ * run two steps per launch) chunk heights 8..32 by timing 2 reps steps of
+ * two-step launches, each from a snapshot of the state (restored
+ * afterwards), and keeps the fastest; ms_per_step (may be NULL) receives the
+ * best time per step of the path the batch runs (two-step launches where
+ * they apply).  Allocates a snapshot of the populations for the call. */
 int lbm_ltne_batch_autotune(lbm_ltne_batch_t b, int32_t reps, double *ms_per_step);
 int lbm_ltne_batch_destroy(lbm_ltne_batch_t b);
 

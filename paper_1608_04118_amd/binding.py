@@ -107,6 +107,8 @@ def lib():
             "lbm_ltne_batch_set_tiles": ([vp, vp], C.c_int),
             "lbm_ltne_batch_get_tiles": ([vp, vp], C.c_int),
             "lbm_ltne_batch_autotune": ([vp, i32, dp], C.c_int),
+            "lbm_ltne_batch_set_chunks": ([vp, vp], C.c_int),
+            "lbm_ltne_batch_get_chunks": ([vp, vp], C.c_int),
             "lbm_ltne_batch_destroy": ([vp], C.c_int),
             "lbm_ltne_strerror": ([C.c_int], C.c_char_p),
             "lbm_ltne_last_error": ([], C.c_char_p),
@@ -501,6 +503,17 @@ def lbm_ltne_batch_get_tiles(b, n):
     return a
 
 
+def lbm_ltne_batch_set_chunks(b, rows):
+    a = np.ascontiguousarray(np.asarray(rows, dtype=np.int32))
+    _check(lib().lbm_ltne_batch_set_chunks(b, _ptr(a)), "lbm_ltne_batch_set_chunks")
+
+
+def lbm_ltne_batch_get_chunks(b, n):
+    a = np.zeros(n, dtype=np.int32)
+    _check(lib().lbm_ltne_batch_get_chunks(b, _ptr(a)), "lbm_ltne_batch_get_chunks")
+    return a
+
+
 def lbm_ltne_batch_autotune(b, reps=4):
     ms = C.c_double()
     _check(lib().lbm_ltne_batch_autotune(b, int(reps), C.byref(ms)), "lbm_ltne_batch_autotune")
@@ -552,23 +565,32 @@ class Batch:
     def set_tiles(self, shifts):
         lbm_ltne_batch_set_tiles(self.h, shifts)
 
+    def chunks(self):
+        return lbm_ltne_batch_get_chunks(self.h, len(self.ps))
+
+    def set_chunks(self, rows):
+        lbm_ltne_batch_set_chunks(self.h, rows)
+
     def autotune(self, reps=4, cache=None):
-        """Tile widths per size class.  With ``cache`` (a JSON path), a
-        choice stored for this device, precision and lattice width is reused
-        and new choices are added; the key is "gfx950/<precision>/<nx>"."""
+        """Tile widths and two-step chunk heights per size class.  With
+        ``cache`` (a JSON path), a choice stored for this device, precision
+        and lattice width is reused and new choices are added; the key is
+        "gfx950/<precision>/<nx>", the value {"tile": log2 width, "rows":
+        chunk height}."""
         import json
         key = lambda p: "gfx950/%d/%d" % (p.precision, p.nx)
         table = {}
         if cache and os.path.exists(cache):
             with open(cache) as f:
                 table = json.load(f)
-        if table and all(key(p) in table for p in self.ps):
-            self.set_tiles([table[key(p)] for p in self.ps])
+        if table and all(isinstance(table.get(key(p)), dict) for p in self.ps):
+            self.set_tiles([table[key(p)]["tile"] for p in self.ps])
+            self.set_chunks([table[key(p)]["rows"] for p in self.ps])
             return None
         ms = lbm_ltne_batch_autotune(self.h, reps)
         if cache:
-            for p, sh in zip(self.ps, self.tiles()):
-                table[key(p)] = int(sh)
+            for p, sh, rows in zip(self.ps, self.tiles(), self.chunks()):
+                table[key(p)] = {"tile": int(sh), "rows": int(rows)}
             d = os.path.dirname(os.path.abspath(cache))
             os.makedirs(d, exist_ok=True)
             with open(cache, "w") as f:

@@ -23,15 +23,27 @@
 
 namespace ltne {
 
+// Buffers of one lattice as byte offsets into the batch's single allocation,
+// whose base the kernels take as an argument: addresses formed from a kernel
+// argument are known to be global memory, so the loads and stores use a
+// scalar base (pointers read from device memory would be generic and turn
+// every access into a flat one with a 64-bit per-lane address).
 template <typename C>
 struct CavityDesc {
-  void* pop[2];     // population buffers (storage type), ping-pong
-  const C* phi;     // per-node porosity or nullptr
-  const C* hv;      // per-node interphase coefficient or nullptr
-  C* mac;           // macros of the last step (5 planes of nx*ny)
-  int tile_begin;   // first entry of this lattice in the combined tile list
-  int wave_begin;   // first entry of this lattice in the two-step wavefront list
+  long long pop[2];  // population buffers (storage type), ping-pong
+  long long phi;     // per-node porosity, or -1
+  long long hv;      // per-node interphase coefficient, or -1
+  long long mac;     // macros of the last step (5 planes of nx*ny)
+  int tile_begin;    // first entry of this lattice in the combined tile list
+  int wave_begin;    // first entry of this lattice in the two-step wavefront list
+  int rows2;         // chunk height of its two-step wavefronts
+  int pad_;
 };
+
+template <typename T>
+__device__ __forceinline__ T* at_offset(char* base, long long off) {
+  return off < 0 ? nullptr : reinterpret_cast<T*>(base + off);
+}
 
 // Grid barrier state, zeroed by the host before each persistent launch.
 struct BatchCtl {
@@ -42,7 +54,7 @@ struct BatchCtl {
 };
 
 template <typename S, typename C, int F>
-__device__ __forceinline__ void batch_tile(int t, const CavityDesc<C>* __restrict__ cav,
+__device__ __forceinline__ void batch_tile(char* base, int t, const CavityDesc<C>* __restrict__ cav,
                                            const StepConsts<C>* __restrict__ ks,
                                            const int* __restrict__ tile_cav, int parity, bool macros,
                                            uint32_t step) {
@@ -57,24 +69,31 @@ __device__ __forceinline__ void batch_tile(int t, const CavityDesc<C>* __restric
   const int x = tx * tw + (static_cast<int>(threadIdx.x) & (tw - 1));
   const int y0 = ty * th * kRows + (static_cast<int>(threadIdx.x) >> k.tm.tw_shift);
   if (x >= k.nx) return;
-  const S* src = static_cast<const S*>(d.pop[parity]);
-  S* dst = static_cast<S*>(d.pop[parity ^ 1]);
+  const S* src = at_offset<const S>(base, d.pop[parity]);
+  S* dst = at_offset<S>(base, d.pop[parity ^ 1]);
+  const C* phi = at_offset<const C>(base, d.phi);
+  const C* hv = at_offset<const C>(base, d.hv);
 #pragma unroll
   for (int r = 0; r < kRows; ++r) {
     const int y = y0 + r * th;
     if (y >= k.ny) continue;
     if (macros)
-      node_update<S, C, F | kMacros>(x, y, src, dst, d.phi, d.hv, d.mac, nullptr, nullptr, k, step);
+      node_update<S, C, F | kMacros>(x, y, src, dst, phi, hv, at_offset<C>(base, d.mac), nullptr, nullptr, k,
+                                     step);
     else
-      node_update<S, C, F>(x, y, src, dst, d.phi, d.hv, nullptr, nullptr, nullptr, k, step);
+      node_update<S, C, F>(x, y, src, dst, phi, hv, nullptr, nullptr, nullptr, k, step);
   }
 }
 
 // Grid-wide barrier for a co-resident (cooperative) grid.  Every wave waits
-// for its own stores, thread 0 of each workgroup releases them device-wide,
-// arrives, and waits for the generation to move on -- at most spin_limit
-// polls, after which it raises the error flag and reports failure so the
-// whole grid leaves the step loop.
+// for its own stores; thread 0 of each workgroup releases them device-wide
+// (one agent-scope release: the write-back of its XCD's L2) and arrives with
+// a relaxed increment.  The last to arrive acquires (so it has seen every
+// workgroup's release), releases again and publishes the new generation;
+// the others poll the generation with relaxed loads (an acquiring load would
+// invalidate the L2 at every poll) and acquire once when it moves on -- at
+// most spin_limit polls, after which a waiter raises the error flag and
+// reports failure so the whole grid leaves the step loop.
 __device__ __forceinline__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks, unsigned& gen,
                                              unsigned spin_limit) {
   __shared__ int ok;
@@ -82,16 +101,17 @@ __device__ __forceinline__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks, un
   __syncthreads();
   if (threadIdx.x == 0) {
     ok = 1;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned target = gen + 1;
-    const unsigned arrived =
-        __hip_atomic_fetch_add(&ctl->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned arrived = __hip_atomic_fetch_add(&ctl->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
     if (arrived == nblocks) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __hip_atomic_store(&ctl->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl->generation, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&ctl->generation, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       unsigned spins = 0;
-      while (__hip_atomic_load(&ctl->generation, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      while (__hip_atomic_load(&ctl->generation, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         if (++spins > spin_limit ||
             __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
           __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -100,9 +120,9 @@ __device__ __forceinline__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks, un
         }
         __builtin_amdgcn_s_sleep(8);
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     gen = target;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
   return ok != 0;
@@ -114,7 +134,7 @@ __device__ __forceinline__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks, un
 // the kernel does one step and needs no barrier.
 template <typename S, typename C, int F>
 __global__ __launch_bounds__(kBlock) void batch_kernel(
-    const CavityDesc<C>* __restrict__ cav, const StepConsts<C>* __restrict__ ks,
+    char* base, const CavityDesc<C>* __restrict__ cav, const StepConsts<C>* __restrict__ ks,
     const int* __restrict__ tile_cav, int ntiles, int nsteps, int parity0, int macros_last,
     BatchCtl* ctl, unsigned spin_limit, uint32_t step0) {
   const int xcd = blockIdx.x & (kXcds - 1);
@@ -128,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(
     const int parity = (parity0 + s) & 1;
     const bool macros = macros_last && (s == nsteps - 1);
     for (int t = t0 + slot; t < t1; t += slots)
-      batch_tile<S, C, F>(t, cav, ks, tile_cav, parity, macros, step0 + static_cast<uint32_t>(s));
+      batch_tile<S, C, F>(base, t, cav, ks, tile_cav, parity, macros, step0 + static_cast<uint32_t>(s));
     if (s + 1 < nsteps && !grid_barrier(ctl, gridDim.x, gen, spin_limit)) return;
   }
 }
@@ -137,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(
 // strip and chunk w - wave_begin of lattice wave_cav[w], as the
 // single-lattice two-step kernel does.
 template <int F>
-__global__ __launch_bounds__(kStep2Block) void batch2_kernel(const CavityDesc<float>* __restrict__ cav,
+__global__ __launch_bounds__(kStep2Block) void batch2_kernel(char* base, const CavityDesc<float>* __restrict__ cav,
                                                         const StepConsts<float>* __restrict__ ks,
                                                         const int* __restrict__ wave_cav, int nwaves, int per_xcd,
                                                         int parity, uint32_t step) {
@@ -145,26 +165,84 @@ __global__ __launch_bounds__(kStep2Block) void batch2_kernel(const CavityDesc<fl
   const int blk = (b & (kXcds - 1)) * per_xcd + (b >> 3);
   const int wl = static_cast<int>(threadIdx.x) >> 6;
   const int wave = blk * (kStep2Block / 64) + wl;
-  // each wavefront's lattice's binary64 temperature constants in LDS (see
-  // step2_kernel), copied by its own lanes before the workgroup barrier
+  if (wave >= nwaves) return;  // whole wavefronts
+  const int c = __builtin_amdgcn_readfirstlane(wave_cav[wave]);
+  const StepConsts<float>& k = ks[c];
+  // this wavefront's lattice's binary64 temperature constants in LDS (see
+  // step2_kernel), copied by its own lanes into its own slot.  No workgroup
+  // barrier: a wavefront's LDS operations execute in order, so its reads see
+  // its own writes (and a barrier would make the compiler treat the
+  // parameter table as possibly written, loading it into vector registers).
   __shared__ ThermalK<double> kts[kStep2Block / 64];
-  const int c = wave < nwaves ? __builtin_amdgcn_readfirstlane(wave_cav[wave]) : 0;
   {
     constexpr int words = sizeof(ThermalK<double>) / 8;
     static_assert(sizeof(ThermalK<double>) % 8 == 0 && words <= 64, "constant block too large");
     const int lane = static_cast<int>(threadIdx.x) & 63;
-    if (wave < nwaves && lane < words)
-      reinterpret_cast<unsigned long long*>(&kts[wl])[lane] =
-          reinterpret_cast<const unsigned long long*>(&ks[c].td)[lane];
+    if (lane < words)
+      reinterpret_cast<unsigned long long*>(&kts[wl])[lane] = reinterpret_cast<const unsigned long long*>(&k.td)[lane];
+    __builtin_amdgcn_wave_barrier();
   }
-  __syncthreads();
-  if (wave >= nwaves) return;  // whole wavefronts
-  const StepConsts<float>& k = ks[c];
   const CavityDesc<float>& d = cav[c];
   const int local = wave - d.wave_begin;
   const int nstrips = (k.nx + step2_out(k.px) - 1) / step2_out(k.px);
-  step2_wave<F>(static_cast<const float*>(d.pop[parity]), static_cast<float*>(d.pop[parity ^ 1]), d.phi, d.hv, k,
-                kts[wl], local % nstrips, local / nstrips, kBatch2Rows, step);
+  step2_wave<F>(at_offset<const float>(base, d.pop[parity]), at_offset<float>(base, d.pop[parity ^ 1]),
+                at_offset<const float>(base, d.phi), at_offset<const float>(base, d.hv), k,
+                kts[wl], local % nstrips, local / nstrips, d.rows2, step);
+}
+
+// Threads per workgroup of the persistent two-step kernel: one workgroup of
+// eight wavefronts fills a CU at two wavefronts per SIMD, so the grid
+// barrier has one participant per CU.
+constexpr int kPersistBlock = 512;
+
+// Every pair of steps of every lattice (FP32 form) in one persistent
+// cooperative launch, with one grid barrier per pair: the wavefront work
+// items of the two-step launches (lattice strips and chunks) are split into
+// 8 contiguous ranges, one per XCD, and the wavefronts of that XCD's
+// workgroups stride through its range.  The parameter table is read through
+// the constant address space, so the barriers' fences do not make the
+// compiler reload it into vector registers.
+template <int F>
+__global__ __launch_bounds__(kPersistBlock) void batch2p_kernel(
+    char* base, const CavityDesc<float>* __restrict__ cav, const StepConsts<float>* __restrict__ ks_generic,
+    const int* __restrict__ wave_cav, int nwaves, int npairs, int parity0, BatchCtl* ctl, unsigned spin_limit,
+    uint32_t step0) {
+  typedef __attribute__((address_space(4))) const StepConsts<float> ConstK;
+  ConstK* ks = (ConstK*)ks_generic;
+  const int xcd = blockIdx.x & (kXcds - 1);
+  const int slot = blockIdx.x >> 3;
+  const int slots = gridDim.x >> 3;
+  constexpr int wpb = kPersistBlock / 64;
+  const int wl = static_cast<int>(threadIdx.x) >> 6;
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  const int per = (nwaves + kXcds - 1) / kXcds;
+  const int w0 = xcd * per;
+  const int w1 = min(nwaves, w0 + per);
+  __shared__ ThermalK<double> kts[wpb];
+  constexpr int words = sizeof(ThermalK<double>) / 8;
+  static_assert(sizeof(ThermalK<double>) % 8 == 0 && words <= 64, "constant block too large");
+  unsigned gen = 0;
+  for (int s = 0; s < npairs; ++s) {
+    const int parity = (parity0 + s) & 1;
+    for (int w = w0 + slot * wpb + wl; w < w1; w += slots * wpb) {
+      const int c = __builtin_amdgcn_readfirstlane(wave_cav[w]);
+      const StepConsts<float>& k = *(const StepConsts<float>*)&ks[c];
+      // this item's lattice constants into the wavefront's own LDS slot (its
+      // LDS operations execute in order; see batch2_kernel)
+      if (lane < words)
+        reinterpret_cast<unsigned long long*>(&kts[wl])[lane] =
+            reinterpret_cast<const unsigned long long*>(&k.td)[lane];
+      __builtin_amdgcn_wave_barrier();
+      const CavityDesc<float>& d = cav[c];
+      const int local = w - d.wave_begin;
+      const int nstrips = (k.nx + step2_out(k.px) - 1) / step2_out(k.px);
+      step2_wave<F>(at_offset<const float>(base, d.pop[parity]), at_offset<float>(base, d.pop[parity ^ 1]),
+                    at_offset<const float>(base, d.phi), at_offset<const float>(base, d.hv), k, kts[wl],
+                    local % nstrips, local / nstrips, d.rows2, step0 + 2u * static_cast<uint32_t>(s));
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (s + 1 < npairs && !grid_barrier(ctl, gridDim.x, gen, spin_limit)) return;
+  }
 }
 
 }  // namespace ltne
@@ -179,12 +257,13 @@ struct lbm_ltne_batch {
   std::vector<lbm_ltne_params> p;
   std::vector<lbm_ltne_derived> d;
   std::vector<int> shift;  // tile width shift per lattice
+  std::vector<int> rows2;  // chunk height of the two-step launches per lattice
   char* base = nullptr;    // all device memory of the batch
   size_t bytes = 0;
   std::vector<size_t> off_pop0, off_pop1, off_phi, off_hv, off_mac;
   size_t off_cav = 0, off_consts = 0, off_tiles = 0, off_waves = 0, off_ctl = 0, off_result = 0;
-  int nwaves2 = 0;    // wavefronts of a two-step launch over every lattice
-  int nwaves2_min = 0;  // the same at the smallest chunk height (decides whether to use it)
+  int nwaves2 = 0;    // wavefronts of a two-step launch over every lattice (current chunk heights)
+  int nwaves2_min = 0;  // the same at the smallest chunk height (decides whether to use it; table size)
   int ntiles = 0;
   int max_tiles = 0;
   int fields = 0;     // kPhiField / kHvField if any lattice has that field
@@ -192,6 +271,7 @@ struct lbm_ltne_batch {
   int64_t steps = 0;
   int persistent = 0; // 1: cooperative persistent launch, 0: one launch per step (default, faster)
   int grid = 0;       // workgroups of the persistent launch
+  int grid2 = 0;      // workgroups of the persistent two-step launch (FP32)
   size_t consts_bytes = 0, desc_bytes = 0;
   long long nodes = 0;
 
@@ -212,21 +292,24 @@ int upload_tables_t(lbm_ltne_batch* b) {
   std::vector<CavityDesc<C>> cav(b->n);
   std::vector<int> tile_cav, wave_cav;
   tile_cav.reserve(b->max_tiles);
-  wave_cav.reserve(b->nwaves2);
+  wave_cav.reserve(b->nwaves2_min);
   for (int i = 0; i < b->n; ++i) {
     fill_step_consts(b->p[i], b->d[i], &ks[i]);
     ks[i].tm = make_tiles(b->p[i].nx, b->p[i].ny, b->precision, b->shift[i]);
-    cav[i].pop[0] = b->base + b->off_pop0[i];
-    cav[i].pop[1] = b->base + b->off_pop1[i];
-    cav[i].phi = b->off_phi[i] ? reinterpret_cast<const C*>(b->base + b->off_phi[i]) : nullptr;
-    cav[i].hv = b->off_hv[i] ? reinterpret_cast<const C*>(b->base + b->off_hv[i]) : nullptr;
-    cav[i].mac = reinterpret_cast<C*>(b->base + b->off_mac[i]);
+    cav[i].pop[0] = static_cast<long long>(b->off_pop0[i]);
+    cav[i].pop[1] = static_cast<long long>(b->off_pop1[i]);
+    cav[i].phi = b->off_phi[i] ? static_cast<long long>(b->off_phi[i]) : -1;
+    cav[i].hv = b->off_hv[i] ? static_cast<long long>(b->off_hv[i]) : -1;
+    cav[i].mac = static_cast<long long>(b->off_mac[i]);
     cav[i].tile_begin = static_cast<int>(tile_cav.size());
     for (int t = 0; t < ks[i].tm.ntiles; ++t) tile_cav.push_back(i);
     cav[i].wave_begin = static_cast<int>(wave_cav.size());
-    for (int w = 0; w < step2_waves(b->p[i].nx, b->p[i].ny, b->p[i].periodic_x, kBatch2Rows); ++w)
+    cav[i].rows2 = b->rows2[i];
+    cav[i].pad_ = 0;
+    for (int w = 0; w < step2_waves(b->p[i].nx, b->p[i].ny, b->p[i].periodic_x, b->rows2[i]); ++w)
       wave_cav.push_back(i);
   }
+  b->nwaves2 = static_cast<int>(wave_cav.size());
   b->ntiles = static_cast<int>(tile_cav.size());
   HIP_TRY(hipMemcpyAsync(b->base + b->off_consts, ks.data(), ks.size() * sizeof(ks[0]),
                          hipMemcpyHostToDevice, b->stream));
@@ -266,11 +349,20 @@ const void* batch_function(const lbm_ltne_batch* b) {
   return pick_fn<_Float16, float>(b->fields);
 }
 
+const void* batch2p_function(const lbm_ltne_batch* b) {
+  switch (b->fields) {
+    case kPhiField: return reinterpret_cast<const void*>(&batch2p_kernel<kPhiField>);
+    case kHvField: return reinterpret_cast<const void*>(&batch2p_kernel<kHvField>);
+    case kPhiField | kHvField: return reinterpret_cast<const void*>(&batch2p_kernel<kPhiField | kHvField>);
+    default: return reinterpret_cast<const void*>(&batch2p_kernel<0>);
+  }
+}
+
 // Workgroups that can be resident at once (multiple of 8), for the
 // cooperative launch.
-int resident_grid(const lbm_ltne_batch* b, int* out) {
+int resident_grid(const lbm_ltne_batch* b, int* out, const void* fn = nullptr, int block = kBlock) {
   int per_cu = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_function(b), kBlock, 0));
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn ? fn : batch_function(b), block, 0));
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, b->device));
   int g = per_cu * prop.multiProcessorCount;
@@ -290,19 +382,19 @@ hipError_t launch_batch2(const lbm_ltne_batch* b, int parity, uint32_t step) {
   const dim3 grid(kXcds * per_xcd), block(kStep2Block);
   switch (b->fields) {
     case kPhiField:
-      hipLaunchKernelGGL(batch2_kernel<kPhiField>, grid, block, 0, b->stream, cav, ks, waves, b->nwaves2, per_xcd,
+      hipLaunchKernelGGL(batch2_kernel<kPhiField>, grid, block, 0, b->stream, b->base, cav, ks, waves, b->nwaves2, per_xcd,
                          parity, step);
       break;
     case kHvField:
-      hipLaunchKernelGGL(batch2_kernel<kHvField>, grid, block, 0, b->stream, cav, ks, waves, b->nwaves2, per_xcd,
+      hipLaunchKernelGGL(batch2_kernel<kHvField>, grid, block, 0, b->stream, b->base, cav, ks, waves, b->nwaves2, per_xcd,
                          parity, step);
       break;
     case kPhiField | kHvField:
-      hipLaunchKernelGGL(batch2_kernel<kPhiField | kHvField>, grid, block, 0, b->stream, cav, ks, waves, b->nwaves2,
+      hipLaunchKernelGGL(batch2_kernel<kPhiField | kHvField>, grid, block, 0, b->stream, b->base, cav, ks, waves, b->nwaves2,
                          per_xcd, parity, step);
       break;
     default:
-      hipLaunchKernelGGL(batch2_kernel<0>, grid, block, 0, b->stream, cav, ks, waves, b->nwaves2, per_xcd, parity,
+      hipLaunchKernelGGL(batch2_kernel<0>, grid, block, 0, b->stream, b->base, cav, ks, waves, b->nwaves2, per_xcd, parity,
                          step);
   }
   return hipGetLastError();
@@ -314,23 +406,50 @@ hipError_t launch_batch2(const lbm_ltne_batch* b, int parity, uint32_t step) {
 // only (the tile widths it chooses apply to them).
 int launch_batch(lbm_ltne_batch* b, int nsteps, int macros_last, bool two_step = true) {
   const void* fn = batch_function(b);
+  char* base = b->base;
   const void* cav = b->base + b->off_cav;
   const void* ks = b->base + b->off_consts;
   const void* tiles = b->base + b->off_tiles;
   BatchCtl* ctl = reinterpret_cast<BatchCtl*>(b->base + b->off_ctl);
   int ntiles = b->ntiles;
   unsigned spin = kSpinLimit;
-  if (b->persistent) {
+  const bool two_ok = two_step && b->precision == LBM_FP32 && b->nwaves2_min >= LTNE_STEP2_MIN_WAVES;
+  if (b->persistent && two_ok) {
+    // the pairs of steps in one persistent launch, then the remaining single
+    // step (the one that writes the macros) as an ordinary launch
+    int npairs = (nsteps - (macros_last ? 1 : 0)) / 2;
+    int parity = b->parity;
+    if (npairs > 0) {
+      HIP_TRY(hipMemsetAsync(ctl, 0, sizeof(BatchCtl), b->stream));
+      const void* waves = b->base + b->off_waves;
+      int nw = b->nwaves2;
+      uint32_t step0 = static_cast<uint32_t>(b->steps + 1);
+      void* args[] = {&base, &cav, &ks, &waves, &nw, &npairs, &parity, &ctl, &spin, &step0};
+      HIP_TRY(hipLaunchCooperativeKernel(batch2p_function(b), dim3(b->grid2), dim3(kPersistBlock), args, 0,
+                                         b->stream));
+      parity = (parity + npairs) & 1;
+    }
+    const int per = (ntiles + kXcds - 1) / kXcds;
+    for (int s = 2 * npairs; s < nsteps; ++s) {
+      int one = 1;
+      int mac = (macros_last && s == nsteps - 1) ? 1 : 0;
+      uint32_t st = static_cast<uint32_t>(b->steps + 1 + s);
+      void* args[] = {&base, &cav, &ks, &tiles, &ntiles, &one, &parity, &mac, &ctl, &spin, &st};
+      HIP_TRY(hipLaunchKernel(fn, dim3(kXcds * per), dim3(kBlock), args, 0, b->stream));
+      parity ^= 1;
+    }
+    b->parity = parity;
+  } else if (b->persistent) {
     HIP_TRY(hipMemsetAsync(ctl, 0, sizeof(BatchCtl), b->stream));
     int parity = b->parity;
     uint32_t step0 = static_cast<uint32_t>(b->steps + 1);
-    void* args[] = {&cav, &ks, &tiles, &ntiles, &nsteps, &parity, &macros_last, &ctl, &spin, &step0};
+    void* args[] = {&base, &cav, &ks, &tiles, &ntiles, &nsteps, &parity, &macros_last, &ctl, &spin, &step0};
     HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(b->grid), dim3(kBlock), args, 0, b->stream));
     b->parity = (b->parity + nsteps) & 1;
   } else {
     const int per = (ntiles + kXcds - 1) / kXcds;
     const int grid = kXcds * per;  // one tile per workgroup per step
-    const bool two = two_step && b->precision == LBM_FP32 && b->nwaves2_min >= LTNE_STEP2_MIN_WAVES;
+    const bool two = two_ok;
     const int last_single = macros_last ? 1 : 0;
     int parity = b->parity;
     for (int s = 0; s < nsteps;) {
@@ -342,7 +461,7 @@ int launch_batch(lbm_ltne_batch* b, int nsteps, int macros_last, bool two_step =
         int one = 1;
         int mac = (macros_last && s == nsteps - 1) ? 1 : 0;
         uint32_t st = step0;
-        void* args[] = {&cav, &ks, &tiles, &ntiles, &one, &parity, &mac, &ctl, &spin, &st};
+        void* args[] = {&base, &cav, &ks, &tiles, &ntiles, &one, &parity, &mac, &ctl, &spin, &st};
         HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, b->stream));
         s += 1;
       }
@@ -459,6 +578,7 @@ int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params* ps, const double* co
   b->p.assign(ps, ps + n);
   b->d = ds;
   b->shift.assign(n, 0);
+  b->rows2.assign(n, kBatch2Rows);
   for (int i = 0; i < n; ++i) {
     if (phi_fields && phi_fields[i]) b->fields |= kPhiField;
     if (Hv_fields && Hv_fields[i]) b->fields |= kHvField;
@@ -485,7 +605,6 @@ int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params* ps, const double* co
     int most = 0;  // the tile table must hold the tiles of any width choice
     for (int sh = 6; sh <= 8; ++sh) most = std::max(most, make_tiles(ps[i].nx, ps[i].ny, precision, sh).ntiles);
     b->max_tiles += most;
-    b->nwaves2 += step2_waves(ps[i].nx, ps[i].ny, ps[i].periodic_x, kBatch2Rows);
     b->nwaves2_min += step2_waves(ps[i].nx, ps[i].ny, ps[i].periodic_x, kStep2MinRows);
   }
   const bool cdouble = compute_bytes(precision) == 8;
@@ -494,7 +613,7 @@ int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params* ps, const double* co
   b->off_consts = o; o += align_up(n * b->consts_bytes, kAlign);
   b->off_cav = o; o += align_up(n * b->desc_bytes, kAlign);
   b->off_tiles = o; o += align_up(static_cast<size_t>(b->max_tiles) * sizeof(int), kAlign);
-  b->off_waves = o; o += align_up(static_cast<size_t>(b->nwaves2) * sizeof(int), kAlign);
+  b->off_waves = o; o += align_up(static_cast<size_t>(b->nwaves2_min) * sizeof(int), kAlign);
   b->off_ctl = o; o += kAlign;
   b->off_result = o; o += kAlign;
   b->bytes = o;
@@ -526,6 +645,7 @@ int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params* ps, const double* co
   }
   if (rc == LBM_OK) rc = upload_tables(b);
   if (rc == LBM_OK) rc = resident_grid(b, &b->grid);
+  if (rc == LBM_OK && precision == LBM_FP32) rc = resident_grid(b, &b->grid2, batch2p_function(b), kPersistBlock);
 
   if (rc == LBM_OK) {
     hipError_t e = hipMemsetAsync(b->base + b->off_ctl, 0, sizeof(BatchCtl), b->stream);
@@ -558,7 +678,7 @@ int lbm_ltne_batch_step(lbm_ltne_batch_t b, int64_t nsteps) {
 
 int lbm_ltne_batch_set_mode(lbm_ltne_batch_t b, int32_t persistent) {
   if (!b) return set_error(LBM_EINVAL, "batch is NULL");
-  if (persistent && b->grid < kXcds)
+  if (persistent && (b->grid < kXcds || (b->precision == LBM_FP32 && b->grid2 < kXcds)))
     return set_error(LBM_EUNSUPPORTED, "no resident grid for a persistent launch");
   b->persistent = persistent ? 1 : 0;
   return LBM_OK;
@@ -569,7 +689,7 @@ int lbm_ltne_batch_info(lbm_ltne_batch_t b, int64_t* nodes, int32_t* tiles, int3
   if (!b) return set_error(LBM_EINVAL, "batch is NULL");
   if (nodes) *nodes = b->nodes;
   if (tiles) *tiles = b->ntiles;
-  if (grid) *grid = b->grid;
+  if (grid) *grid = (b->precision == LBM_FP32 && b->nwaves2_min >= LTNE_STEP2_MIN_WAVES) ? b->grid2 : b->grid;
   if (persistent) *persistent = b->persistent;
   return LBM_OK;
 }
@@ -587,6 +707,23 @@ int lbm_ltne_batch_get_tiles(lbm_ltne_batch_t b, int32_t* tile_shift) {
   if (!b || !tile_shift) return set_error(LBM_EINVAL, "batch or shifts NULL");
   for (int i = 0; i < b->n; ++i)
     tile_shift[i] = make_tiles(b->p[i].nx, b->p[i].ny, b->precision, b->shift[i]).tw_shift;
+  return LBM_OK;
+}
+
+int lbm_ltne_batch_set_chunks(lbm_ltne_batch_t b, const int32_t* rows) {
+  if (!b || !rows) return set_error(LBM_EINVAL, "batch or chunk heights NULL");
+  for (int i = 0; i < b->n; ++i) {
+    bool ok = rows[i] == 0;
+    for (int r : kStep2RowChoices) ok = ok || rows[i] == r;
+    if (!ok) return set_error(LBM_EINVAL, "chunk height %d of lattice %d not in {0, 8, 12, 16, 24, 32}", rows[i], i);
+  }
+  for (int i = 0; i < b->n; ++i) b->rows2[i] = rows[i] ? rows[i] : kBatch2Rows;
+  return upload_tables(b);
+}
+
+int lbm_ltne_batch_get_chunks(lbm_ltne_batch_t b, int32_t* rows) {
+  if (!b || !rows) return set_error(LBM_EINVAL, "batch or chunk heights NULL");
+  for (int i = 0; i < b->n; ++i) rows[i] = b->rows2[i];
   return LBM_OK;
 }
 
@@ -662,6 +799,46 @@ int lbm_ltne_batch_autotune(lbm_ltne_batch_t b, int32_t reps, double* ms_per_ste
       }
     }
     for (int i : kv.second) b->shift[i] = best_shift;
+  }
+  // The chunk heights of the two-step launches (FP32 form), timed on the
+  // path that runs: pairs of steps per launch over every lattice.
+  const bool two = b->precision == LBM_FP32 && b->nwaves2_min >= LTNE_STEP2_MIN_WAVES;
+  if (two && rc == LBM_OK) {
+    auto trial2 = [&](float* ms) -> int {
+      int r = copy_state(false);
+      if (r != LBM_OK) return r;
+      b->parity = parity0;
+      r = launch_batch(b, 2, 0, true);  // warm-up
+      if (r != LBM_OK) return r;
+      HIP_TRY(hipEventRecord(e0, b->stream));
+      r = launch_batch(b, 2 * reps, 0, true);
+      if (r != LBM_OK) return r;
+      HIP_TRY(hipEventRecord(e1, b->stream));
+      HIP_TRY(hipEventSynchronize(e1));
+      HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+      *ms /= static_cast<float>(2 * reps);
+      b->parity = parity0;
+      return LBM_OK;
+    };
+    rc = upload_tables(b);
+    if (rc == LBM_OK) rc = trial2(&best);
+    for (auto& kv : classes) {
+      if (rc != LBM_OK) break;
+      int best_rows = b->rows2[kv.second[0]];
+      for (int r : kStep2RowChoices) {
+        if (r == best_rows) continue;
+        for (int i : kv.second) b->rows2[i] = r;
+        rc = upload_tables(b);
+        float ms = 0.0f;
+        if (rc == LBM_OK) rc = trial2(&ms);
+        if (rc != LBM_OK) break;
+        if (ms < best) {
+          best = ms;
+          best_rows = r;
+        }
+      }
+      for (int i : kv.second) b->rows2[i] = best_rows;
+    }
   }
   if (rc == LBM_OK) rc = upload_tables(b);
   const int rc2 = copy_state(false);

@@ -64,6 +64,16 @@ __host__ __device__ constexpr uint32_t mix32(uint32_t x) {
   return x;
 }
 
+// A device pointer read from memory (a batch's per-lattice buffers) is a
+// generic pointer, and loads through it become flat-address instructions
+// with 64-bit per-lane addresses.  Passing it through the global address
+// space tells the compiler where it points, so it uses global loads and
+// stores with a scalar base.
+template <typename T>
+__device__ __forceinline__ T* as_global(T* p) {
+  return (T*)((__attribute__((address_space(1))) T*)p);
+}
+
 // Flags of the fused step kernel.
 constexpr int kPhiField = 1;  // per-node porosity
 constexpr int kHvField = 2;   // per-node interphase coefficient

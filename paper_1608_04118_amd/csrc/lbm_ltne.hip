@@ -34,6 +34,7 @@ struct lbm_ltne {
   StepConsts<double> kd{};
   StepConsts<float> kf{};
   std::vector<double> tf0, ts0;  // initial temperature fields (if given), for the adjoint
+  hipGraphExec_t seq[2] = {nullptr, nullptr};  // recorded runs of kSeqSteps steps from buffer 0 / 1
 
   void* pop(int i) const { return base + lay.off_pop[i]; }
   void* mac(int i) const { return base + lay.off_mac[i]; }
@@ -46,6 +47,8 @@ struct lbm_ltne {
   unsigned long long* diverged() const {
     return reinterpret_cast<unsigned long long*>(base + lay.off_result + 16 * sizeof(double));
   }
+  // step number of the next step of a recorded run (see step_seq_kernel)
+  uint32_t* step_base() const { return reinterpret_cast<uint32_t*>(base + lay.off_result + 24 * sizeof(double)); }
   long long n() const { return static_cast<long long>(p.nx) * p.ny; }
 };
 
@@ -194,8 +197,93 @@ int upload_field(const lbm_ltne* h, const double* src, void* dst) {
 
 void release(lbm_ltne* h) {
   if (!h) return;
+  for (hipGraphExec_t& g : h->seq)
+    if (g) (void)hipGraphExecDestroy(g);
   if (h->owns && h->base) (void)hipFree(h->base);
   delete h;
+}
+
+// Lattices whose single steps are short enough that launching them one by
+// one costs a large part of their time run their steps in recorded runs of
+// kSeqSteps launches (a HIP graph replayed as a whole), when they do not take
+// two steps per launch and no step of the run is checked under diag_every.
+constexpr int kSeqSteps = 32;  // even: a run starts and ends on the same buffer
+constexpr long long kSeqMaxNodes = 1LL << 20;
+
+template <typename S, typename C, int F>
+int build_seq_t(lbm_ltne* h, const StepConsts<C>& k, int start) {
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipGraphCreate(&g, 0));
+  hipGraphNode_t prev = nullptr;
+  int rc = LBM_OK;
+  const dim3 grid(grid_blocks(k.tm)), block(kBlock);
+  for (int j = 0; j < kSeqSteps && rc == LBM_OK; ++j) {
+    const S* src = static_cast<const S*>(h->pop((start + j) & 1));
+    S* dst = static_cast<S*>(h->pop((start + j + 1) & 1));
+    const C* phi = static_cast<const C*>(h->phi());
+    const C* hv = static_cast<const C*>(h->hv());
+    StepConsts<C> kk = k;
+    const uint32_t* base = h->step_base();
+    uint32_t off = static_cast<uint32_t>(j);
+    void* args[] = {&src, &dst, &phi, &hv, &kk, &base, &off};
+    hipKernelNodeParams np{};
+    np.func = reinterpret_cast<void*>(&step_seq_kernel<S, C, F>);
+    np.gridDim = grid;
+    np.blockDim = block;
+    np.sharedMemBytes = 0;
+    np.kernelParams = args;
+    np.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    const hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &np);
+    if (e != hipSuccess) rc = set_error(LBM_EHIP, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+    prev = node;
+  }
+  if (rc == LBM_OK) {
+    uint32_t* base = h->step_base();
+    uint32_t n = kSeqSteps;
+    int add = 1;
+    void* args[] = {&base, &n, &add};
+    hipKernelNodeParams np{};
+    np.func = reinterpret_cast<void*>(&step_base_kernel);
+    np.gridDim = dim3(1);
+    np.blockDim = dim3(64);
+    np.sharedMemBytes = 0;
+    np.kernelParams = args;
+    np.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    const hipError_t e = hipGraphAddKernelNode(&node, g, &prev, 1, &np);
+    if (e != hipSuccess) rc = set_error(LBM_EHIP, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+  }
+  if (rc == LBM_OK) {
+    const hipError_t e = hipGraphInstantiate(&h->seq[start], g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      h->seq[start] = nullptr;
+      rc = set_error(LBM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+  }
+  (void)hipGraphDestroy(g);
+  return rc;
+}
+
+template <typename S, typename C>
+int build_seq_p(lbm_ltne* h, const StepConsts<C>& k, int start) {
+  switch ((h->has_phi ? kPhiField : 0) | (h->has_hv ? kHvField : 0)) {
+    case kPhiField: return build_seq_t<S, C, kPhiField>(h, k, start);
+    case kHvField: return build_seq_t<S, C, kHvField>(h, k, start);
+    case kPhiField | kHvField: return build_seq_t<S, C, kPhiField | kHvField>(h, k, start);
+    default: return build_seq_t<S, C, 0>(h, k, start);
+  }
+}
+
+// The recorded run starting from population buffer `start`, built on first use.
+int seq_graph(lbm_ltne* h, int start) {
+  if (h->seq[start]) return LBM_OK;
+  switch (h->p.precision) {
+    case LBM_FP64: return build_seq_p<double, double>(h, h->kd, start);
+    case LBM_FP32: return build_seq_p<float, float>(h, h->kf, start);
+    case LBM_FP32SR: return build_seq_p<float, double>(h, h->kd, start);
+    default: return build_seq_p<_Float16, float>(h, h->kf, start);
+  }
 }
 
 // Workgroups of the binary64 sums over the macros.
@@ -383,6 +471,20 @@ int lbm_ltne_step(lbm_ltne_t h, int64_t nsteps) {
   auto checked = [de](int64_t t) { return de > 0 && t % de == 0; };
   void* scratch_mac = h->mac(1 - h->mcur);  // overwritten by the call's last step
   int64_t s = 0;
+  // recorded runs of kSeqSteps single steps on small lattices
+  if (!pairs && de == 0 && h->n() <= kSeqMaxNodes && nsteps - 1 >= kSeqSteps) {
+    hipLaunchKernelGGL(step_base_kernel, dim3(1), dim3(64), 0, h->stream, h->step_base(),
+                       static_cast<uint32_t>(h->steps + 1), 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(LBM_EHIP, "step base: %s", hipGetErrorString(e));
+    for (; s + kSeqSteps <= nsteps - 1; s += kSeqSteps) {
+      const int rc = seq_graph(h, h->cur);
+      if (rc != LBM_OK) return rc;
+      e = hipGraphLaunch(h->seq[h->cur], h->stream);
+      if (e != hipSuccess) return set_error(LBM_EHIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+      h->steps += kSeqSteps;  // an even number of steps: the state stays in buffer cur
+    }
+  }
   while (s < nsteps) {
     const int64_t t = h->steps + 1;  // number of the next step
     // a pair of steps in one launch while more than the last step (which

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void sums_kernel(const C* __restrict__ mac,
 
 // Sums nparts partial rows into out[0..kSums) (one workgroup).  Internal
 // linkage: every translation unit that launches it has its own copy.
-static __global__ __launch_bounds__(kBlock) void sums_final_kernel(const double* __restrict__ partial,
+[[maybe_unused]] static __global__ __launch_bounds__(kBlock) void sums_final_kernel(const double* __restrict__ partial,
                                                             int nparts, double* __restrict__ out) {
   __shared__ double lds[kSums][kWaves];
   double v[kSums] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -83,7 +83,7 @@ static __global__ __launch_bounds__(kBlock) void sums_final_kernel(const double*
 // Divergence check of a step: sums the mass and energy partials of
 // sums_kernel (one workgroup) and, if either is not finite, records the
 // step number in *flag unless an earlier step is already recorded.
-static __global__ __launch_bounds__(kBlock) void finite_check_kernel(const double* __restrict__ partial,
+[[maybe_unused]] static __global__ __launch_bounds__(kBlock) void finite_check_kernel(const double* __restrict__ partial,
                                                               int nparts,
                                                               unsigned long long* __restrict__ flag,
                                                               unsigned long long step) {

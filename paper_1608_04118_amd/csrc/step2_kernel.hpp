@@ -201,6 +201,7 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
   advance(y_lo - 1, pa, wa);
   fetch(y_lo + 1, pa);
   advance(y_lo, pb, wb);
+#pragma nounroll
   for (int y = y_lo; y < y_hi; ++y) {
     advance(y + 1, pa, wc);
     if (y + 1 < y_hi) fetch(y + 2, pa);

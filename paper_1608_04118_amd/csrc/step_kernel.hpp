@@ -703,13 +703,15 @@ __device__ __forceinline__ void node_update_with(
   }
 }
 
-// Workgroup b runs tile (b % 8) * per_xcd + b / 8 (see TileMap); each thread
-// updates kRows nodes of one column of the tile, kRowStride rows apart.
+// The nodes of the tile that workgroup b runs: tile (b % 8) * per_xcd + b / 8
+// (see TileMap); each thread updates kRows nodes of one column of the tile,
+// kRowStride rows apart.
 template <typename S, typename C, int F>
-__global__ __launch_bounds__(kBlock) void step_kernel(
-    const S* __restrict__ src, S* __restrict__ dst, const C* __restrict__ phi_field,
-    const C* __restrict__ hv_field, C* __restrict__ mac, const C* __restrict__ init_tf,
-    const C* __restrict__ init_ts, const StepConsts<C> k, const uint32_t step, C* __restrict__ rec = nullptr) {
+__device__ __forceinline__ void step_tile(const S* __restrict__ src, S* __restrict__ dst,
+                                          const C* __restrict__ phi_field, const C* __restrict__ hv_field,
+                                          C* __restrict__ mac, const C* __restrict__ init_tf,
+                                          const C* __restrict__ init_ts, const StepConsts<C>& k,
+                                          const uint32_t step, C* __restrict__ rec) {
   const int b = blockIdx.x;
   const int t = kXcdRemap ? (b & (kXcds - 1)) * k.tm.per_xcd + (b >> 3) : b;
   if (t >= k.tm.ntiles) return;
@@ -725,6 +727,32 @@ __global__ __launch_bounds__(kBlock) void step_kernel(
     const int y = y0 + r * th;
     if (y < k.ny) node_update<S, C, F>(x, y, src, dst, phi_field, hv_field, mac, init_tf, init_ts, k, step, rec);
   }
+}
+
+template <typename S, typename C, int F>
+__global__ __launch_bounds__(kBlock) void step_kernel(
+    const S* __restrict__ src, S* __restrict__ dst, const C* __restrict__ phi_field,
+    const C* __restrict__ hv_field, C* __restrict__ mac, const C* __restrict__ init_tf,
+    const C* __restrict__ init_ts, const StepConsts<C> k, const uint32_t step, C* __restrict__ rec = nullptr) {
+  step_tile<S, C, F>(src, dst, phi_field, hv_field, mac, init_tf, init_ts, k, step, rec);
+}
+
+// The step as a node of a recorded sequence of steps (a HIP graph replayed
+// many times): its step number, which seeds the stochastic rounding, is
+// *step_base + offset, the base living in device memory and advanced by
+// step_advance_kernel at the end of every replay.
+template <typename S, typename C, int F>
+__global__ __launch_bounds__(kBlock) void step_seq_kernel(const S* __restrict__ src, S* __restrict__ dst,
+                                                          const C* __restrict__ phi_field,
+                                                          const C* __restrict__ hv_field, const StepConsts<C> k,
+                                                          const uint32_t* __restrict__ step_base,
+                                                          const uint32_t offset) {
+  step_tile<S, C, F>(src, dst, phi_field, hv_field, nullptr, nullptr, nullptr, k, *step_base + offset, nullptr);
+}
+
+// Sets (add = 0) or advances (add = 1) the device step base by n.
+[[maybe_unused]] static __global__ void step_base_kernel(uint32_t* __restrict__ step_base, uint32_t n, int add) {
+  if (threadIdx.x == 0) *step_base = add ? *step_base + n : n;
 }
 
 }  // namespace ltne
