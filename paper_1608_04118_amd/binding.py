@@ -381,8 +381,10 @@ class Lattice:
             self.h = None
         self._pool = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    # The finalizing test is bound at definition: during interpreter teardown
+    # this module's globals (sys among them) may already be cleared.
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()
@@ -602,8 +604,10 @@ class Batch:
             lbm_ltne_batch_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    # The finalizing test is bound at definition: during interpreter teardown
+    # this module's globals (sys among them) may already be cleared.
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()

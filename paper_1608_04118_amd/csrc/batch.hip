@@ -264,6 +264,7 @@ struct lbm_ltne_batch {
   size_t off_cav = 0, off_consts = 0, off_tiles = 0, off_waves = 0, off_ctl = 0, off_result = 0;
   int nwaves2 = 0;    // wavefronts of a two-step launch over every lattice (current chunk heights)
   int nwaves2_min = 0;  // the same at the smallest chunk height (decides whether to use it; table size)
+  bool step2_addr = true;  // every lattice's rows addressable by the two-step kernel
   int ntiles = 0;
   int max_tiles = 0;
   int fields = 0;     // kPhiField / kHvField if any lattice has that field
@@ -400,6 +401,12 @@ hipError_t launch_batch2(const lbm_ltne_batch* b, int parity, uint32_t step) {
   return hipGetLastError();
 }
 
+// FP32 batches with enough wavefronts at the smallest chunk height, whose
+// rows the two-step kernel can address, run pairs of steps per launch.
+bool two_step_ok(const lbm_ltne_batch* b) {
+  return b->precision == LBM_FP32 && b->step2_addr && b->nwaves2_min >= LTNE_STEP2_MIN_WAVES;
+}
+
 // nsteps steps of every lattice.  Per-step mode: the FP32 form runs pairs
 // of steps in one two-step launch (two_step, and enough wavefronts) except
 // for a last step that writes the macros; the autotuner times single steps
@@ -413,7 +420,7 @@ int launch_batch(lbm_ltne_batch* b, int nsteps, int macros_last, bool two_step =
   BatchCtl* ctl = reinterpret_cast<BatchCtl*>(b->base + b->off_ctl);
   int ntiles = b->ntiles;
   unsigned spin = kSpinLimit;
-  const bool two_ok = two_step && b->precision == LBM_FP32 && b->nwaves2_min >= LTNE_STEP2_MIN_WAVES;
+  const bool two_ok = two_step && two_step_ok(b);
   if (b->persistent && two_ok) {
     // the pairs of steps in one persistent launch, then the remaining single
     // step (the one that writes the macros) as an ordinary launch
@@ -606,6 +613,7 @@ int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params* ps, const double* co
     for (int sh = 6; sh <= 8; ++sh) most = std::max(most, make_tiles(ps[i].nx, ps[i].ny, precision, sh).ntiles);
     b->max_tiles += most;
     b->nwaves2_min += step2_waves(ps[i].nx, ps[i].ny, ps[i].periodic_x, kStep2MinRows);
+    b->step2_addr = b->step2_addr && step2_addressable(ps[i].nx);
   }
   const bool cdouble = compute_bytes(precision) == 8;
   b->consts_bytes = (cdouble ? sizeof(StepConsts<double>) : sizeof(StepConsts<float>));
@@ -689,7 +697,7 @@ int lbm_ltne_batch_info(lbm_ltne_batch_t b, int64_t* nodes, int32_t* tiles, int3
   if (!b) return set_error(LBM_EINVAL, "batch is NULL");
   if (nodes) *nodes = b->nodes;
   if (tiles) *tiles = b->ntiles;
-  if (grid) *grid = (b->precision == LBM_FP32 && b->nwaves2_min >= LTNE_STEP2_MIN_WAVES) ? b->grid2 : b->grid;
+  if (grid) *grid = two_step_ok(b) ? b->grid2 : b->grid;
   if (persistent) *persistent = b->persistent;
   return LBM_OK;
 }
@@ -802,7 +810,7 @@ int lbm_ltne_batch_autotune(lbm_ltne_batch_t b, int32_t reps, double* ms_per_ste
   }
   // The chunk heights of the two-step launches (FP32 form), timed on the
   // path that runs: pairs of steps per launch over every lattice.
-  const bool two = b->precision == LBM_FP32 && b->nwaves2_min >= LTNE_STEP2_MIN_WAVES;
+  const bool two = two_step_ok(b);
   if (two && rc == LBM_OK) {
     auto trial2 = [&](float* ms) -> int {
       int r = copy_state(false);

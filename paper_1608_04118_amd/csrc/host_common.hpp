@@ -40,6 +40,12 @@ inline size_t compute_bytes(int precision) { return (precision == LBM_FP64 || pr
 // with one plane per population).
 inline long long pop_row_elems(int nx) { return static_cast<long long>(align_up(static_cast<size_t>(nx), 64)); }
 inline long long pop_elems(int nx, int ny) { return kPlanes * pop_row_elems(nx) * ny; }
+// The two-step kernel addresses a lattice row (its kPlanes population rows)
+// through one buffer resource with 32-bit byte offsets: the row must span
+// less than 2^31 bytes of binary32 populations.
+inline bool step2_addressable(int nx) {
+  return kPlanes * pop_row_elems(nx) * static_cast<long long>(sizeof(float)) < (1LL << 31);
+}
 
 struct Layout {
   size_t pop_bytes, field_bytes, mac_bytes;

@@ -89,6 +89,83 @@ struct Step2Map {
   int per_xcd;  // workgroups per XCD
 };
 
+// Loads and stores of the two-step kernel through buffer resources: one
+// resource per lattice row (its 19 population rows), the population's offset
+// in the scalar offset operand and the lane's column in the vector offset,
+// so no vector instruction is spent forming 64-bit addresses.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float* row, long long rs) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(row), static_cast<short>(0),
+                                           static_cast<int>(rs * static_cast<long long>(sizeof(float))),
+                                           0x00020000);
+}
+
+struct BufPull {
+  const float* __restrict__ src;
+  __device__ __forceinline__ void operator()(int xc, int yc, const StepConsts<float>& k, float (&v)[kPlanes]) const {
+    const int nx = k.nx, ny = k.ny;
+    const int yu = __builtin_amdgcn_readfirstlane(yc);
+    int xm = xc - 1, xp = xc + 1, ym = yu - 1, yp = yu + 1;
+    if (k.px) {
+      xm = (xc == 0) ? nx - 1 : xm;
+      xp = (xc == nx - 1) ? 0 : xp;
+    }
+    if (k.py) {
+      ym = (yu == 0) ? ny - 1 : ym;
+      yp = (yu == ny - 1) ? 0 : yp;
+    }
+    const __amdgpu_buffer_rsrc_t r0 = row_rsrc(src + yu * k.rs, k.rs);
+    const __amdgpu_buffer_rsrc_t rm = row_rsrc(src + ym * k.rs, k.rs);
+    const __amdgpu_buffer_rsrc_t rp = row_rsrc(src + yp * k.rs, k.rs);
+    const int Q = static_cast<int>(k.qs) * 4;
+    const int oc = xc * 4, om = xm * 4, op = xp * 4;
+    auto ld = [&](__amdgpu_buffer_rsrc_t r, int vo, int q) {
+      return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, q * Q, 0));
+    };
+    v[0] = ld(r0, oc, 0);
+    v[1] = ld(r0, om, 1);
+    v[2] = ld(rm, oc, 2);
+    v[3] = ld(r0, op, 3);
+    v[4] = ld(rp, oc, 4);
+    v[5] = ld(rm, om, 5);
+    v[6] = ld(rm, op, 6);
+    v[7] = ld(rp, op, 7);
+    v[8] = ld(rp, om, 8);
+    v[9] = ld(r0, oc, 9);
+    v[10] = ld(r0, om, 10);
+    v[11] = ld(rm, oc, 11);
+    v[12] = ld(r0, op, 12);
+    v[13] = ld(rp, oc, 13);
+    v[14] = ld(r0, oc, 14);
+    v[15] = ld(r0, om, 15);
+    v[16] = ld(rm, oc, 16);
+    v[17] = ld(r0, op, 17);
+    v[18] = ld(rp, oc, 18);
+  }
+};
+
+struct BufPut {
+  // cache policy of the stores: the non-temporal bit when kStep2NtStore
+  static constexpr int kNtAux = kStep2NtStore ? 2 : 0;
+  float* __restrict__ dst;
+  __amdgpu_buffer_rsrc_t r;
+  int vo = 0, Q = 0;
+  __device__ __forceinline__ void begin(int x, int y, const StepConsts<float>& k) {
+    r = row_rsrc(dst + static_cast<long long>(__builtin_amdgcn_readfirstlane(y)) * k.rs, k.rs);
+    vo = x * 4;
+    Q = static_cast<int>(k.qs) * 4;
+  }
+  __device__ __forceinline__ void st(int i, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, vo, i * Q, kNtAux);
+  }
+  template <typename VA, typename VB>
+  __device__ __forceinline__ void pair(int i, VA va, VA, int j, VB vb, VB, uint32_t w, half2_t&) {
+    st(i, to_storage<float>(va, w << 16));
+    st(j, to_storage<float>(vb, w));
+  }
+  template <typename V>
+  __device__ __forceinline__ void single(int i, V v, V, uint32_t w) { st(i, to_storage<float>(v, w)); }
+};
+
 // Copies a constant block into LDS, one 8-byte word per thread.
 template <typename K>
 __device__ __forceinline__ void copy_to_lds(const K& src, K& dst) {
@@ -158,7 +235,7 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
   }
   if (y_lo >= y_hi) return;
 
-  const GlobalPull<float, float> gpull{src};
+  const BufPull gpull{src};
   // row r at this lane's column, wrapped on a periodic axis; ok: a node exists
   auto row_of = [&](int r, bool& ok) {
     ok = colok;
@@ -167,27 +244,28 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
     return r;
   };
   // the pulls of node (col, r) at time t (a wall node pulls those of its
-  // inward neighbour), issued one row ahead of their use so the loads
-  // overlap the arithmetic of the row before
-  auto fetch = [&](int r, float (&v)[kPlanes]) {
+  // inward neighbour) and the porosity and H_v there, issued one row ahead
+  // of their use so the loads overlap the arithmetic of the row before
+  auto fetch = [&](int r, float (&v)[kPlanes], CenterFields<float>& cf) {
     bool ok;
     r = row_of(r, ok);
     if (ok) {
       const int xc = (!k.px && col == 0) ? 1 : ((!k.px && col == nx - 1) ? nx - 2 : col);
       const int yc = (!k.py && r == 0) ? 1 : ((!k.py && r == ny - 1) ? ny - 2 : r);
       gpull(xc, yc, k, v);
+      cf = load_center<float, F>(phi_field, hv_field, yc * nx + xc, k);
     }
   };
-  // node (col, r) at time t + 1 from its fetched pulls into w; zeros where
-  // there is no node
-  auto advance = [&](int r, const float (&v)[kPlanes], float (&w)[kPlanes]) {
+  // node (col, r) at time t + 1 from its fetched pulls and fields into w;
+  // zeros where there is no node
+  auto advance = [&](int r, const float (&v)[kPlanes], const CenterFields<float>& cf, float (&w)[kPlanes]) {
     bool ok;
     r = row_of(r, ok);
     if (ok) {
       const RegPull<float> rp{v};
       RegPut<float> put{w};
       node_update_with<float, float, F>(col, r, rp, put, phi_field, hv_field, nullptr, nullptr, nullptr, k, step,
-                                        nullptr, kt);
+                                        nullptr, kt, &cf);
     } else {
 #pragma unroll
       for (int i = 0; i < kPlanes; ++i) w[i] = 0.0f;
@@ -196,15 +274,20 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
 
   float wa[kPlanes], wb[kPlanes], wc[kPlanes];  // time t + 1 at rows y - 1, y, y + 1
   float pa[kPlanes], pb[kPlanes];               // fetched pulls of two rows
-  fetch(y_lo - 1, pa);
-  fetch(y_lo, pb);
-  advance(y_lo - 1, pa, wa);
-  fetch(y_lo + 1, pa);
-  advance(y_lo, pb, wb);
+  CenterFields<float> fa{}, fb{};               // and the fields fetched with them
+  fetch(y_lo - 1, pa, fa);
+  fetch(y_lo, pb, fb);
+  advance(y_lo - 1, pa, fa, wa);
+  fetch(y_lo + 1, pa, fa);
+  advance(y_lo, pb, fb, wb);
+  // fields of node (col, y), pulled node of the output update at row y (on
+  // an output lane col = xo, and a wall row pulls from row y as well)
+  CenterFields<float> fy = fb;
 #pragma nounroll
   for (int y = y_lo; y < y_hi; ++y) {
-    advance(y + 1, pa, wc);
-    if (y + 1 < y_hi) fetch(y + 2, pa);
+    advance(y + 1, pa, fa, wc);
+    const CenterFields<float> fn = fa;
+    if (y + 1 < y_hi) fetch(y + 2, pa, fa);
     // pulls of node (xo + dx, y) at time t + 1: population i from column
     // xo + dx - e_ix (lane offset) and row y - e_iy (window row)
     float g[kPlanes];
@@ -217,14 +300,14 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
     }
     if (outlane) {
       const RegPull<float> rpull{g};
-      GlobalPut<float, float, kStep2NtStore> put{dst};
+      BufPut put{dst};
       // the node at row y, then the wall row it feeds (one call site)
       const int nrep = (!k.py && (y == 1 || y == ny - 2)) ? 2 : 1;
 #pragma nounroll
       for (int rep = 0; rep < nrep; ++rep) {
         const int yy = rep == 0 ? y : (y == 1 ? 0 : ny - 1);
         node_update_with<float, float, F>(xo, yy, rpull, put, phi_field, hv_field, nullptr, nullptr, nullptr, k,
-                                          step + 1u, nullptr, kt);
+                                          step + 1u, nullptr, kt, &fy);
       }
     }
 #pragma unroll
@@ -232,6 +315,7 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
       wa[i] = wb[i];
       wb[i] = wc[i];
     }
+    fy = fn;
   }
 }
 

@@ -285,15 +285,33 @@ struct GlobalPut {
   __device__ __forceinline__ void single(int i, V v, V s, uint32_t r) { store_pop<NT>(at(drow + i * P, x), v, s, r); }
 };
 
+// Porosity and H_v of the node whose populations a node update pulls (the
+// node itself, or its inward neighbour at a wall).  A caller that reads them
+// ahead, with the populations, passes them in; otherwise the update reads
+// them where it needs them.
+template <typename C>
+struct CenterFields {
+  C phi, hv;
+};
+
+template <typename C, int F>
+__device__ __forceinline__ CenterFields<C> load_center(const C* __restrict__ phi_field,
+                                                       const C* __restrict__ hv_field, const int ic,
+                                                       const StepConsts<C>& k) {
+  return {(F & kPhiField) ? phi_field[ic] : k.phi_u, (F & kHvField) ? hv_field[ic] : k.hv_u};
+}
+
 // kt: the temperature-lattice constants of k (thermal_k), passed apart so a
 // caller can hand in a copy in LDS (the two-step kernel: vector operands that
-// free the scalar registers of the binary64 constants).
+// free the scalar registers of the binary64 constants).  pre: the fields at
+// the pulled node, read ahead by the caller (nullptr: read here).
 template <typename S, typename C, int F, class Pull, class Put>
 __device__ __forceinline__ void node_update_with(
     const int x, const int y, const Pull& pull, Put& put,
     const C* __restrict__ phi_field, const C* __restrict__ hv_field, C* __restrict__ mac,
     const C* __restrict__ init_tf, const C* __restrict__ init_ts, const StepConsts<C>& k,
-    const uint32_t step, C* __restrict__ rec, const ThermalK<thermal_t<S, C>>& kt);
+    const uint32_t step, C* __restrict__ rec, const ThermalK<thermal_t<S, C>>& kt,
+    const CenterFields<C>* pre = nullptr);
 
 // One node update: pull, macros, walls, collisions, store.  step numbers
 // the time step being computed (0: initialisation); with a narrow storage
@@ -315,7 +333,8 @@ __device__ __forceinline__ void node_update_with(
     const int x, const int y, const Pull& pull, Put& put,
     const C* __restrict__ phi_field, const C* __restrict__ hv_field, C* __restrict__ mac,
     const C* __restrict__ init_tf, const C* __restrict__ init_ts, const StepConsts<C>& k,
-    const uint32_t step, C* __restrict__ rec, const ThermalK<thermal_t<S, C>>& kt) {
+    const uint32_t step, C* __restrict__ rec, const ThermalK<thermal_t<S, C>>& kt,
+    const CenterFields<C>* pre) {
   const int nx = k.nx, ny = k.ny;
 
   // Wall classification and the node whose post-streaming populations this
@@ -327,8 +346,9 @@ __device__ __forceinline__ void node_update_with(
   const int yc = wy ? (y == 0 ? 1 : ny - 2) : y;
   const int ic = yc * nx + xc;
 
-  const C phi_c = (F & kPhiField) ? phi_field[ic] : k.phi_u;
-  const C hv_c = (F & kHvField) ? hv_field[ic] : k.hv_u;
+  const CenterFields<C> cf = pre ? *pre : load_center<C, F>(phi_field, hv_field, ic, k);
+  const C phi_c = cf.phi;
+  const C hv_c = cf.hv;
 
   // T: arithmetic type of the temperature lattices (see ThermalArith)
   using T = thermal_t<S, C>;
