@@ -143,6 +143,23 @@ struct BufPull {
   }
 };
 
+// One field value (porosity or H_v) of node (xc, yc) through a buffer
+// resource over the field's row, so a wavefront's loads are all of one kind.
+__device__ __forceinline__ float buf_field(const float* __restrict__ f, int xc, int yc, int nx) {
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(f + static_cast<long long>(__builtin_amdgcn_readfirstlane(yc)) * nx), static_cast<short>(0),
+      nx * static_cast<int>(sizeof(float)), 0x00020000);
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, xc * 4, 0, 0));
+}
+
+template <int F>
+__device__ __forceinline__ CenterFields<float> buf_center(const float* __restrict__ phi_field,
+                                                          const float* __restrict__ hv_field, int xc, int yc,
+                                                          const StepConsts<float>& k) {
+  return {(F & kPhiField) ? buf_field(phi_field, xc, yc, k.nx) : k.phi_u,
+          (F & kHvField) ? buf_field(hv_field, xc, yc, k.nx) : k.hv_u};
+}
+
 struct BufPut {
   // cache policy of the stores: the non-temporal bit when kStep2NtStore
   static constexpr int kNtAux = kStep2NtStore ? 2 : 0;
@@ -202,63 +219,89 @@ struct RegPull {
   }
 };
 
-// One wavefront's strip and chunk of a lattice.
-// kt: the lattice's temperature constants, a copy in LDS (see the kernels).
-template <int F>
-__device__ __forceinline__ void step2_wave(const float* __restrict__ src, float* __restrict__ dst,
-                                           const float* __restrict__ phi_field, const float* __restrict__ hv_field,
-                                           const StepConsts<float>& k, const ThermalK<double>& kt,
-                                           const int strip, const int chunk, const int rows,
-                                           const uint32_t step) {
-  const int lane = static_cast<int>(threadIdx.x) & 63;
-  const int nx = k.nx, ny = k.ny;
-  const int halo = step2_halo(k.px), out = step2_out(k.px);
-  const int x0 = strip * out;
-  // column of this lane at time t + 1
-  int col = x0 - halo + lane;
-  bool colok = true;
-  if (k.px) {
-    col %= nx;
-    if (col < 0) col += nx;
-  } else {
-    colok = col >= 0 && col < nx;
-  }
-  // output column and the column offset of its pulls (x walls pull inward)
-  const int xo = x0 - halo + lane;
-  const bool outlane = lane >= halo && lane < halo + out && xo < nx;
-  const int dx = (!k.px && xo == 0) ? 1 : ((!k.px && xo == nx - 1) ? -1 : 0);
-  // rows of this chunk; a wall row is updated with its inward neighbour row
-  int y_lo = chunk * rows, y_hi = y_lo + rows < ny ? y_lo + rows : ny;
-  if (!k.py) {
-    y_lo = y_lo > 1 ? y_lo : 1;
-    y_hi = y_hi < ny - 1 ? y_hi : ny - 1;
-  }
-  if (y_lo >= y_hi) return;
+// A copy of fields already used (so loaded) that the compiler must keep in
+// registers of its own.  Carrying loaded values from row to row otherwise
+// lets it load the next row's values into other registers and copy them back
+// at the end of the row, and that copy waits for every memory access issued
+// before it, stores included.
+__device__ __forceinline__ CenterFields<float> detach(CenterFields<float> f) {
+  asm volatile("" : "+v"(f.phi), "+v"(f.hv));
+  return f;
+}
 
-  const BufPull gpull{src};
+// The work of one lane of a strip and chunk: its columns, the chunk's rows,
+// and the three parts of the update (fetch, intermediate level, output).
+template <int F>
+struct Step2Lane {
+  const float* __restrict__ src;
+  float* __restrict__ dst;
+  const float* __restrict__ phi_field;
+  const float* __restrict__ hv_field;
+  const StepConsts<float>& k;
+  const ThermalK<double>& kt;
+  uint32_t step;
+  int lane, col, xo, dx, y_lo, y_hi;
+  bool colok, outlane;
+
+  __device__ __forceinline__ Step2Lane(const float* __restrict__ src_, float* __restrict__ dst_,
+                                       const float* __restrict__ phi_, const float* __restrict__ hv_,
+                                       const StepConsts<float>& k_, const ThermalK<double>& kt_, const int strip,
+                                       const int chunk, const int rows, const uint32_t step_)
+      : src(src_), dst(dst_), phi_field(phi_), hv_field(hv_), k(k_), kt(kt_), step(step_) {
+    lane = static_cast<int>(threadIdx.x) & 63;
+    const int nx = k.nx, ny = k.ny;
+    const int halo = step2_halo(k.px), out = step2_out(k.px);
+    const int x0 = strip * out;
+    // column of this lane at time t + 1
+    col = x0 - halo + lane;
+    colok = true;
+    if (k.px) {
+      col %= nx;
+      if (col < 0) col += nx;
+    } else {
+      colok = col >= 0 && col < nx;
+    }
+    // output column and the column offset of its pulls (x walls pull inward)
+    xo = x0 - halo + lane;
+    outlane = lane >= halo && lane < halo + out && xo < nx;
+    dx = (!k.px && xo == 0) ? 1 : ((!k.px && xo == nx - 1) ? -1 : 0);
+    // rows of this chunk; a wall row is updated with its inward neighbour row
+    y_lo = chunk * rows;
+    y_hi = y_lo + rows < ny ? y_lo + rows : ny;
+    if (!k.py) {
+      y_lo = y_lo > 1 ? y_lo : 1;
+      y_hi = y_hi < ny - 1 ? y_hi : ny - 1;
+    }
+  }
+
   // row r at this lane's column, wrapped on a periodic axis; ok: a node exists
-  auto row_of = [&](int r, bool& ok) {
+  __device__ __forceinline__ int row_of(int r, bool& ok) const {
     ok = colok;
-    if (k.py) return r < 0 ? r + ny : (r >= ny ? r - ny : r);
-    ok = ok && r >= 0 && r < ny;
+    if (k.py) return r < 0 ? r + k.ny : (r >= k.ny ? r - k.ny : r);
+    ok = ok && r >= 0 && r < k.ny;
     return r;
-  };
+  }
+
   // the pulls of node (col, r) at time t (a wall node pulls those of its
-  // inward neighbour) and the porosity and H_v there, issued one row ahead
-  // of their use so the loads overlap the arithmetic of the row before
-  auto fetch = [&](int r, float (&v)[kPlanes], CenterFields<float>& cf) {
+  // inward neighbour) and the porosity and H_v there, issued ahead of their
+  // use so the loads overlap arithmetic
+  __device__ __forceinline__ void fetch(int r, float (&v)[kPlanes], CenterFields<float>& cf) const {
     bool ok;
     r = row_of(r, ok);
     if (ok) {
+      const int nx = k.nx, ny = k.ny;
       const int xc = (!k.px && col == 0) ? 1 : ((!k.px && col == nx - 1) ? nx - 2 : col);
       const int yc = (!k.py && r == 0) ? 1 : ((!k.py && r == ny - 1) ? ny - 2 : r);
+      const BufPull gpull{src};
       gpull(xc, yc, k, v);
-      cf = load_center<float, F>(phi_field, hv_field, yc * nx + xc, k);
+      cf = buf_center<F>(phi_field, hv_field, xc, yc, k);
     }
-  };
+  }
+
   // node (col, r) at time t + 1 from its fetched pulls and fields into w;
   // zeros where there is no node
-  auto advance = [&](int r, const float (&v)[kPlanes], const CenterFields<float>& cf, float (&w)[kPlanes]) {
+  __device__ __forceinline__ void advance(int r, const float (&v)[kPlanes], const CenterFields<float>& cf,
+                                          float (&w)[kPlanes]) const {
     bool ok;
     r = row_of(r, ok);
     if (ok) {
@@ -270,24 +313,58 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
 #pragma unroll
       for (int i = 0; i < kPlanes; ++i) w[i] = 0.0f;
     }
-  };
+  }
+
+  // node (xo, y) at time t + 2 from its gathered pulls g (time t + 1) and the
+  // fields fy of its pulled node, stored; then the wall row it feeds (one
+  // call site)
+  __device__ __forceinline__ void output(int y, const float (&g)[kPlanes], const CenterFields<float>& fy) const {
+    const RegPull<float> rpull{g};
+    BufPut put{dst};
+    const int ny = k.ny;
+    const int nrep = (!k.py && (y == 1 || y == ny - 2)) ? 2 : 1;
+#pragma nounroll
+    for (int rep = 0; rep < nrep; ++rep) {
+      const int yy = rep == 0 ? y : (y == 1 ? 0 : ny - 1);
+      node_update_with<float, float, F>(xo, yy, rpull, put, phi_field, hv_field, nullptr, nullptr, nullptr, k,
+                                        step + 1u, nullptr, kt, &fy);
+    }
+  }
+};
+
+// One wavefront's strip and chunk of a lattice.  At row y it
+//   1. updates its column at row y + 1 to time t + 1 from device memory,
+//      keeping the 19 results in registers: a window of rows y - 1, y, y + 1;
+//   2. gathers the pulls of its node at row y from the window, the column
+//      offsets by cross-lane permutes;
+//   3. updates the node at row y to time t + 2 and stores it.
+// kt: the lattice's temperature constants, a copy in LDS (see the kernels).
+template <int F>
+__device__ __forceinline__ void step2_wave(const float* __restrict__ src, float* __restrict__ dst,
+                                           const float* __restrict__ phi_field, const float* __restrict__ hv_field,
+                                           const StepConsts<float>& k, const ThermalK<double>& kt,
+                                           const int strip, const int chunk, const int rows,
+                                           const uint32_t step) {
+  const Step2Lane<F> L(src, dst, phi_field, hv_field, k, kt, strip, chunk, rows, step);
+  const int y_lo = L.y_lo, y_hi = L.y_hi, lane = L.lane, dx = L.dx;
+  if (y_lo >= y_hi) return;
 
   float wa[kPlanes], wb[kPlanes], wc[kPlanes];  // time t + 1 at rows y - 1, y, y + 1
   float pa[kPlanes], pb[kPlanes];               // fetched pulls of two rows
   CenterFields<float> fa{}, fb{};               // and the fields fetched with them
-  fetch(y_lo - 1, pa, fa);
-  fetch(y_lo, pb, fb);
-  advance(y_lo - 1, pa, fa, wa);
-  fetch(y_lo + 1, pa, fa);
-  advance(y_lo, pb, fb, wb);
-  // fields of node (col, y), pulled node of the output update at row y (on
-  // an output lane col = xo, and a wall row pulls from row y as well)
-  CenterFields<float> fy = fb;
+  L.fetch(y_lo - 1, pa, fa);
+  L.fetch(y_lo, pb, fb);
+  L.advance(y_lo - 1, pa, fa, wa);
+  L.fetch(y_lo + 1, pa, fa);
+  L.advance(y_lo, pb, fb, wb);
+  // fields of node (col, y), the pulled node of the output update at row y
+  // (on an output lane col = xo, and a wall row pulls from row y as well)
+  CenterFields<float> fy = detach(fb);
 #pragma nounroll
   for (int y = y_lo; y < y_hi; ++y) {
-    advance(y + 1, pa, fa, wc);
-    const CenterFields<float> fn = fa;
-    if (y + 1 < y_hi) fetch(y + 2, pa, fa);
+    L.advance(y + 1, pa, fa, wc);
+    const CenterFields<float> fn = detach(fa);
+    if (y + 1 < y_hi) L.fetch(y + 2, pa, fa);
     // pulls of node (xo + dx, y) at time t + 1: population i from column
     // xo + dx - e_ix (lane offset) and row y - e_iy (window row)
     float g[kPlanes];
@@ -298,18 +375,7 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
       const int sl = (lane + dx - vel_x(q)) & 63;
       g[i] = __shfl(v, sl, 64);
     }
-    if (outlane) {
-      const RegPull<float> rpull{g};
-      BufPut put{dst};
-      // the node at row y, then the wall row it feeds (one call site)
-      const int nrep = (!k.py && (y == 1 || y == ny - 2)) ? 2 : 1;
-#pragma nounroll
-      for (int rep = 0; rep < nrep; ++rep) {
-        const int yy = rep == 0 ? y : (y == 1 ? 0 : ny - 1);
-        node_update_with<float, float, F>(xo, yy, rpull, put, phi_field, hv_field, nullptr, nullptr, nullptr, k,
-                                          step + 1u, nullptr, kt, &fy);
-      }
-    }
+    if (L.outlane) L.output(y, g, fy);
 #pragma unroll
     for (int i = 0; i < kPlanes; ++i) {
       wa[i] = wb[i];
