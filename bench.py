@@ -296,7 +296,8 @@ def ingest_counters(fetch_csv: str, write_csv: str, copy_bytes: int, out_path: s
                         "scale": float(scale), "step_bytes": float(np.median(step) * 1024.0 * scale)}
     total = out["FETCH_SIZE"]["step_bytes"] + out["WRITE_SIZE"]["step_bytes"]
     rec = {"f32": {"kernel_hash": kernel_hash(), "bytes_per_launch": total,
-                   "algorithmic_bytes_per_launch": BYTES_PER_LUP["f32"] * N * N * 2,
+                   "must_move_bytes_per_launch": BYTES_PER_LUP["f32"] * N * N,
+                   "one_step_equivalent_bytes_per_launch": BYTES_PER_LUP["f32"] * N * N * 2,
                    "counters": out}}
     with open(out_path, "w") as f:
         json.dump(rec, f, indent=1)

@@ -157,14 +157,14 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(
 // strip and chunk w - wave_begin of lattice wave_cav[w], as the
 // single-lattice two-step kernel does.
 template <int F>
-__global__ __launch_bounds__(kStep2Block) void batch2_kernel(char* base, const CavityDesc<float>* __restrict__ cav,
+__global__ __launch_bounds__(kBatch2Block) void batch2_kernel(char* base, const CavityDesc<float>* __restrict__ cav,
                                                         const StepConsts<float>* __restrict__ ks,
                                                         const int* __restrict__ wave_cav, int nwaves, int per_xcd,
                                                         int parity, uint32_t step) {
   const int b = blockIdx.x;
   const int blk = (b & (kXcds - 1)) * per_xcd + (b >> 3);
   const int wl = static_cast<int>(threadIdx.x) >> 6;
-  const int wave = blk * (kStep2Block / 64) + wl;
+  const int wave = blk * (kBatch2Block / 64) + wl;
   if (wave >= nwaves) return;  // whole wavefronts
   const int c = __builtin_amdgcn_readfirstlane(wave_cav[wave]);
   const StepConsts<float>& k = ks[c];
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kStep2Block) void batch2_kernel(char* base, const C
   // barrier: a wavefront's LDS operations execute in order, so its reads see
   // its own writes (and a barrier would make the compiler treat the
   // parameter table as possibly written, loading it into vector registers).
-  __shared__ ThermalK<double> kts[kStep2Block / 64];
+  __shared__ ThermalK<double> kts[kBatch2Block / 64];
   {
     constexpr int words = sizeof(ThermalK<double>) / 8;
     static_assert(sizeof(ThermalK<double>) % 8 == 0 && words <= 64, "constant block too large");
@@ -378,9 +378,9 @@ hipError_t launch_batch2(const lbm_ltne_batch* b, int parity, uint32_t step) {
   const CavityDesc<float>* cav = reinterpret_cast<const CavityDesc<float>*>(b->base + b->off_cav);
   const StepConsts<float>* ks = reinterpret_cast<const StepConsts<float>*>(b->base + b->off_consts);
   const int* waves = reinterpret_cast<const int*>(b->base + b->off_waves);
-  const int nblocks = (b->nwaves2 + kStep2Block / 64 - 1) / (kStep2Block / 64);
+  const int nblocks = (b->nwaves2 + kBatch2Block / 64 - 1) / (kBatch2Block / 64);
   const int per_xcd = (nblocks + kXcds - 1) / kXcds;
-  const dim3 grid(kXcds * per_xcd), block(kStep2Block);
+  const dim3 grid(kXcds * per_xcd), block(kBatch2Block);
   switch (b->fields) {
     case kPhiField:
       hipLaunchKernelGGL(batch2_kernel<kPhiField>, grid, block, 0, b->stream, b->base, cav, ks, waves, b->nwaves2, per_xcd,

@@ -45,6 +45,16 @@ constexpr int kBatch2Rows = LTNE_BATCH2_ROWS;
 #endif
 constexpr int kStep2Block = LTNE_STEP2_BLOCK;
 static_assert(kStep2Block % 64 == 0 && kStep2Block <= 1024, "whole wavefronts per workgroup");
+// Threads per workgroup of the batched two-step kernel: one wavefront, so a
+// compute unit starts a new strip as soon as any of its wavefronts ends (the
+// strips of small lattices differ in length; on the 256-cavity batch one
+// wavefront per workgroup was 5% faster than four, while a single large
+// lattice runs faster with four neighbouring strips per workgroup).
+#ifndef LTNE_BATCH2_BLOCK
+#define LTNE_BATCH2_BLOCK 64
+#endif
+constexpr int kBatch2Block = LTNE_BATCH2_BLOCK;
+static_assert(kBatch2Block % 64 == 0 && kBatch2Block <= 1024, "whole wavefronts per workgroup");
 // Stores of the two-step kernels: plain, so the L2 merges the partial cache
 // lines written by neighbouring strips (62 or 61 columns wide) before they go
 // to HBM; non-temporal stores were 5% slower on the 8192^2 layer.
@@ -186,7 +196,7 @@ struct BufPut {
 // Copies a constant block into LDS, one 8-byte word per thread.
 template <typename K>
 __device__ __forceinline__ void copy_to_lds(const K& src, K& dst) {
-  static_assert(sizeof(K) % 8 == 0 && sizeof(K) / 8 <= kStep2Block, "constant block too large");
+  static_assert(sizeof(K) % 8 == 0 && sizeof(K) / 8 <= 64, "constant block too large");
   const int t = static_cast<int>(threadIdx.x);
   if (t < static_cast<int>(sizeof(K) / 8))
     reinterpret_cast<unsigned long long*>(&dst)[t] = reinterpret_cast<const unsigned long long*>(&src)[t];
@@ -223,9 +233,12 @@ struct RegPull {
 // registers of its own.  Carrying loaded values from row to row otherwise
 // lets it load the next row's values into other registers and copy them back
 // at the end of the row, and that copy waits for every memory access issued
-// before it, stores included.
+// before it, stores included.  Uniform fields (not loaded) are left as they
+// are, so that what derives from them stays hoisted out of the row loop.
+template <int F>
 __device__ __forceinline__ CenterFields<float> detach(CenterFields<float> f) {
-  asm volatile("" : "+v"(f.phi), "+v"(f.hv));
+  if constexpr ((F & kPhiField) != 0) asm volatile("" : "+v"(f.phi));
+  if constexpr ((F & kHvField) != 0) asm volatile("" : "+v"(f.hv));
   return f;
 }
 
@@ -359,11 +372,11 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
   L.advance(y_lo, pb, fb, wb);
   // fields of node (col, y), the pulled node of the output update at row y
   // (on an output lane col = xo, and a wall row pulls from row y as well)
-  CenterFields<float> fy = detach(fb);
+  CenterFields<float> fy = detach<F>(fb);
 #pragma nounroll
   for (int y = y_lo; y < y_hi; ++y) {
     L.advance(y + 1, pa, fa, wc);
-    const CenterFields<float> fn = detach(fa);
+    const CenterFields<float> fn = detach<F>(fa);
     if (y + 1 < y_hi) L.fetch(y + 2, pa, fa);
     // pulls of node (xo + dx, y) at time t + 1: population i from column
     // xo + dx - e_ix (lane offset) and row y - e_iy (window row)

@@ -84,7 +84,8 @@ def test_ingest_counters_calibrates_by_the_copy(tmp_path, capsys):
     assert c["FETCH_SIZE"]["step_bytes"] == pytest.approx(2.9e6 * 1024 * 2)
     assert c["WRITE_SIZE"]["step_bytes"] == pytest.approx(5.1e6 * 1024)
     assert rec["bytes_per_launch"] == pytest.approx(2.9e6 * 2048 + 5.1e6 * 1024)
-    assert rec["algorithmic_bytes_per_launch"] == 156 * 8192 * 8192 * 2
+    assert rec["must_move_bytes_per_launch"] == 156 * 8192 * 8192
+    assert rec["one_step_equivalent_bytes_per_launch"] == 156 * 8192 * 8192 * 2
     assert rec["kernel_hash"] == bench.kernel_hash()
 
 
