@@ -51,7 +51,11 @@ struct BatchCtl {
   unsigned generation;  // barriers completed
   int error;            // 1: a wait exceeded its spin limit (all workgroups then leave)
   int pad_;
+  // work counters of the persistent two-step kernel: pair s of a launch
+  // hands out the work items of XCD x from next[s % 2][x]
+  unsigned next[2][kXcds];
 };
+static_assert(sizeof(BatchCtl) <= kAlign, "control block larger than its slot");
 
 template <typename S, typename C, int F>
 __device__ __forceinline__ void batch_tile(char* base, int t, const CavityDesc<C>* __restrict__ cav,
@@ -199,9 +203,11 @@ constexpr int kPersistBlock = 512;
 // cooperative launch, with one grid barrier per pair: the wavefront work
 // items of the two-step launches (lattice strips and chunks) are split into
 // 8 contiguous ranges, one per XCD, and the wavefronts of that XCD's
-// workgroups stride through its range.  The parameter table is read through
-// the constant address space, so the barriers' fences do not make the
-// compiler reload it into vector registers.
+// workgroups take the items of its range one at a time from a counter, so
+// that they reach the barrier together however the items' lengths differ.
+// The parameter table is read through the constant address space, so the
+// barriers' fences do not make the compiler reload it into vector
+// registers.
 template <int F>
 __global__ __launch_bounds__(kPersistBlock) void batch2p_kernel(
     char* base, const CavityDesc<float>* __restrict__ cav, const StepConsts<float>* __restrict__ ks_generic,
@@ -211,7 +217,6 @@ __global__ __launch_bounds__(kPersistBlock) void batch2p_kernel(
   ConstK* ks = (ConstK*)ks_generic;
   const int xcd = blockIdx.x & (kXcds - 1);
   const int slot = blockIdx.x >> 3;
-  const int slots = gridDim.x >> 3;
   constexpr int wpb = kPersistBlock / 64;
   const int wl = static_cast<int>(threadIdx.x) >> 6;
   const int lane = static_cast<int>(threadIdx.x) & 63;
@@ -224,7 +229,17 @@ __global__ __launch_bounds__(kPersistBlock) void batch2p_kernel(
   unsigned gen = 0;
   for (int s = 0; s < npairs; ++s) {
     const int parity = (parity0 + s) & 1;
-    for (int w = w0 + slot * wpb + wl; w < w1; w += slots * wpb) {
+    unsigned* next = &ctl->next[s & 1][xcd];
+    // the counter of the next pair, last used by the pair before this one
+    // (finished at the barrier before this pair); the barrier after this
+    // pair publishes the reset
+    if (slot == 0 && threadIdx.x == 0)
+      __hip_atomic_store(&ctl->next[(s + 1) & 1][xcd], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+      unsigned item = 0;
+      if (lane == 0) item = __hip_atomic_fetch_add(next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int w = w0 + static_cast<int>(__builtin_amdgcn_readfirstlane(item));
+      if (w >= w1) break;
       const int c = __builtin_amdgcn_readfirstlane(wave_cav[w]);
       const StepConsts<float>& k = *(const StepConsts<float>*)&ks[c];
       // this item's lattice constants into the wavefront's own LDS slot (its
