@@ -295,10 +295,13 @@ int lbm_ltne_batch_get_chunks(lbm_ltne_batch_t b, int32_t *rows);
 /* Autotuner: for each size class (lattices of equal nx) tries tile widths
  * 64/128/256 by timing reps single-step launches, then (FP32 batches that
  * run two steps per launch) chunk heights 8..32 by timing 2 reps steps of
- * two-step launches, each from a snapshot of the state (restored
- * afterwards), and keeps the fastest; ms_per_step (may be NULL) receives the
- * best time per step of the path the batch runs (two-step launches where
- * they apply).  Allocates a snapshot of the populations for the call. */
+ * two-step launches, then the launch mode (one launch per step or pair of
+ * steps, or one persistent launch; skipped when the device has no resident
+ * grid for it) by timing 2 reps steps of each, every trial from a snapshot
+ * of the state (restored afterwards), and keeps the fastest of each;
+ * ms_per_step (may be NULL) receives the time per step of the chosen
+ * configuration on the path the batch runs (two-step launches where they
+ * apply).  Allocates a snapshot of the populations for the call. */
 int lbm_ltne_batch_autotune(lbm_ltne_batch_t b, int32_t reps, double *ms_per_step);
 int lbm_ltne_batch_destroy(lbm_ltne_batch_t b);
 

@@ -574,11 +574,13 @@ class Batch:
         lbm_ltne_batch_set_chunks(self.h, rows)
 
     def autotune(self, reps=4, cache=None):
-        """Tile widths and two-step chunk heights per size class.  With
-        ``cache`` (a JSON path), a choice stored for this device, precision
-        and lattice width is reused and new choices are added; the key is
-        "gfx950/<precision>/<nx>", the value {"tile": log2 width, "rows":
-        chunk height}."""
+        """Tile widths and two-step chunk heights per size class, then the
+        launch mode of the whole batch.  With ``cache`` (a JSON path), a
+        choice stored for this device, precision and lattice width is reused
+        and new choices are added; the key is "gfx950/<precision>/<nx>", the
+        value {"tile": log2 width, "rows": chunk height}.  The launch mode
+        depends on the whole batch and is not cached: a cache hit keeps the
+        current mode."""
         import json
         key = lambda p: "gfx950/%d/%d" % (p.precision, p.nx)
         table = {}

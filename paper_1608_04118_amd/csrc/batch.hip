@@ -864,6 +864,36 @@ int lbm_ltne_batch_autotune(lbm_ltne_batch_t b, int32_t reps, double* ms_per_ste
     }
   }
   if (rc == LBM_OK) rc = upload_tables(b);
+  // The launch mode, with the shapes chosen: both modes timed over 2 reps
+  // steps of the path each runs (pairs of steps where they apply), from the
+  // snapshot; the faster is kept.  Persistent launches pay off where
+  // launches are a large part of a step (small batches).
+  const bool can_persist = b->grid >= kXcds && !(b->precision == LBM_FP32 && b->grid2 < kXcds);
+  if (rc == LBM_OK && can_persist) {
+    const int mode0 = b->persistent;
+    float ms_mode[2] = {0.0f, 0.0f};
+    for (int m = 0; m < 2 && rc == LBM_OK; ++m) {
+      b->persistent = m;
+      rc = copy_state(false);
+      b->parity = parity0;
+      if (rc == LBM_OK) rc = launch_batch(b, 2, 0, true);  // warm-up
+      if (rc == LBM_OK && hipEventRecord(e0, b->stream) != hipSuccess) rc = set_error(LBM_EHIP, "event record");
+      if (rc == LBM_OK) rc = launch_batch(b, 2 * reps, 0, true);
+      if (rc == LBM_OK && hipEventRecord(e1, b->stream) != hipSuccess) rc = set_error(LBM_EHIP, "event record");
+      if (rc == LBM_OK && hipEventSynchronize(e1) != hipSuccess) rc = set_error(LBM_EHIP, "event sync");
+      if (rc == LBM_OK && hipEventElapsedTime(&ms_mode[m], e0, e1) != hipSuccess)
+        rc = set_error(LBM_EHIP, "event time");
+      if (rc == LBM_OK) rc = check_ctl(b);
+      ms_mode[m] /= static_cast<float>(2 * reps);
+    }
+    b->parity = parity0;
+    if (rc == LBM_OK) {
+      b->persistent = ms_mode[1] < ms_mode[0] ? 1 : 0;
+      best = ms_mode[b->persistent];
+    } else {
+      b->persistent = mode0;
+    }
+  }
   const int rc2 = copy_state(false);
   if (rc == LBM_OK) rc = rc2;
   if (hipStreamSynchronize(b->stream) != hipSuccess && rc == LBM_OK) rc = set_error(LBM_EHIP, "autotune sync");
