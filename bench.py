@@ -334,6 +334,50 @@ def ingest_sq(csv_path: str, out_path: str):
     print(json.dumps(rec, indent=1))
 
 
+def clock_probe(forms=("f32", "f16s", "f64"), samples: int = 6, interval_s: float = 0.4):
+    """Shader and memory clocks (rocm-smi --showclocks) while one form steps
+    the 8192^2 layer continuously (400 steps per call, in a loop on a second
+    thread), sampled after one second of running; idle first."""
+    import subprocess
+    import threading
+    import torch
+    from paper_1608_04118_amd import binding as B
+    from paper_1608_04118_amd import inputs as I
+
+    def sample(n):
+        out = []
+        for _ in range(n):
+            r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=30)
+            out.append([ln.split(":", 1)[1].strip() for ln in r.stdout.splitlines() if "sclk" in ln or "mclk" in ln])
+            time.sleep(interval_s)
+        return out
+
+    res = {"idle": sample(2)}
+    for tag in forms:
+        p, phi, Tf0, Ts0 = I.throughput(n=N, precision=PRECISION[tag])
+        lat = B.Lattice(dict(p, **EXTRA.get(tag, {})), phi=phi, Tf0=Tf0, Ts0=Ts0)
+        lat.step(20)
+        torch.cuda.synchronize()
+        stop = threading.Event()
+
+        def run():
+            while not stop.is_set():
+                lat.step(400)
+                torch.cuda.synchronize()
+        th = threading.Thread(target=run)
+        th.start()
+        time.sleep(1.0)
+        try:
+            res[tag] = sample(samples)
+        finally:
+            stop.set()
+            th.join()
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    return res
+
+
 def cpu_model() -> str:
     """CPU model name of the host (lscpu, else /proc/cpuinfo)."""
     import subprocess
@@ -498,6 +542,8 @@ def main():
     ap.add_argument("--copy-check", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the small-workload rates (64^2 FP64 cavity, 1024^2 FP32 cavity, 1024x256 channel)")
+    ap.add_argument("--clock-probe", action="store_true",
+                    help="only sample the shader clock (rocm-smi) while each form runs (one JSON object)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="convert rocprofv3 FETCH_SIZE / WRITE_SIZE runs into profiles/traffic.json")
     ap.add_argument("--ingest-sq", metavar="SQ_CSV",
@@ -521,6 +567,9 @@ def main():
         sys.exit(2)
     if args.adjoint_only:
         print(json.dumps(time_adjoint()), flush=True)
+        return
+    if args.clock_probe:
+        print(json.dumps(clock_probe()), flush=True)
         return
     from paper_1608_04118_amd import inputs as I
     inputs = I.throughput(n=N, precision=I.FP32)
