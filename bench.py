@@ -378,6 +378,22 @@ def clock_probe(forms=("f32", "f16s", "f64"), samples: int = 6, interval_s: floa
     return res
 
 
+def persist_probe(mode: int, steps: int = 200):
+    """16 cavities of 64^2 (FP32; the single-step batch kernel) stepped in one
+    call in the given launch mode (0: a launch per step, 1: persistent), for
+    counter runs comparing the modes."""
+    from paper_1608_04118_amd import binding as B
+    from paper_1608_04118_amd import inputs as I
+    ps = [I.cavity_small(nx=64, ny=64, precision=I.FP32, Ra=1e4 * (1 + 0.1 * i)) for i in range(16)]
+    bt = B.Batch(ps)
+    bt.set_mode(mode)
+    bt.step(steps)
+    bt.macros(0)  # synchronizes and checks the barrier flag
+    info = bt.info()
+    bt.close()
+    return {"mode": mode, "steps": steps, "grid": info["grid"], "tiles": info["tiles"]}
+
+
 def cpu_model() -> str:
     """CPU model name of the host (lscpu, else /proc/cpuinfo)."""
     import subprocess
@@ -542,6 +558,8 @@ def main():
     ap.add_argument("--copy-check", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the small-workload rates (64^2 FP64 cavity, 1024^2 FP32 cavity, 1024x256 channel)")
+    ap.add_argument("--persist-probe", type=int, choices=(0, 1), default=None,
+                    help="only step a small batch in launch mode 0 or 1 (for counter runs)")
     ap.add_argument("--clock-probe", action="store_true",
                     help="only sample the shader clock (rocm-smi) while each form runs (one JSON object)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -570,6 +588,9 @@ def main():
         return
     if args.clock_probe:
         print(json.dumps(clock_probe()), flush=True)
+        return
+    if args.persist_probe is not None:
+        print(json.dumps(persist_probe(args.persist_probe)), flush=True)
         return
     from paper_1608_04118_amd import inputs as I
     inputs = I.throughput(n=N, precision=I.FP32)
