@@ -382,16 +382,19 @@ def persist_probe(mode: int, steps: int = 200):
     """16 cavities of 64^2 (FP32; the single-step batch kernel) stepped in one
     call in the given launch mode (0: a launch per step, 1: persistent), for
     counter runs comparing the modes."""
+    import torch
     from paper_1608_04118_amd import binding as B
     from paper_1608_04118_amd import inputs as I
     ps = [I.cavity_small(nx=64, ny=64, precision=I.FP32, Ra=1e4 * (1 + 0.1 * i)) for i in range(16)]
     bt = B.Batch(ps)
     bt.set_mode(mode)
-    bt.step(steps)
+    ms = _events_ms(bt.stream, lambda: bt.step(steps))
     bt.macros(0)  # synchronizes and checks the barrier flag
     info = bt.info()
     bt.close()
-    return {"mode": mode, "steps": steps, "grid": info["grid"], "tiles": info["tiles"]}
+    torch.cuda.synchronize()
+    return {"mode": mode, "steps": steps, "us_per_step": round(1e3 * ms / steps, 2), "grid": info["grid"],
+            "tiles": info["tiles"]}
 
 
 def cpu_model() -> str:
