@@ -11,8 +11,9 @@ Eq. 52 correlation and the Sec. 3.2 correction term, are timed on the same
 lattice and reported under "variants".
 
 A step is one time step of all three lattices over the whole lattice.  The
-FP32 forms advance two steps per launch (all but the last step of a call,
-which also writes the macroscopic fields); the other forms one.  Inputs are
+FP32 forms advance two steps per launch (an odd last step of a call
+alone; the call's last launch also writes the macroscopic fields); the
+other forms one.  Inputs are
 resident in device memory before timing starts.  The time of K steps (one
 call) is taken with HIP events on the stream the library queues on, between
 two device synchronisations.
@@ -114,7 +115,7 @@ CUS, CLOCK_HZ = 256, 2.4e9
 VALU_ISSUE_PER_S = CUS * CLOCK_HZ
 
 
-# Forms whose steps run two to a launch (all but the last step of a call)
+# Forms whose steps run two to a launch (an odd last step of a call alone)
 TWO_STEP = ("f32", "f32ext")
 
 
@@ -209,7 +210,7 @@ def time_batch(steps: int, warmup: int, autotune: bool = True):
     return dict(ms_per_step=ms_step, mlups=nodes / (ms_step * 1e-3) / 1e6, achieved_gbs=achieved,
                 frac=achieved / HBM_PEAK_GBS, nodes=nodes, lattices=len(ps), grid=info["grid"],
                 mode=("one persistent launch per call" if chosen else
-                      "launches over all lattices, two steps per launch but the last of a call"),
+                      "launches over all lattices, two steps per launch (an odd last step alone)"),
                 mode_chosen_by="autotuner" if autotune else "default",
                 bytes_note="152 B per node per pair of steps (state read and written once)",
                 launches_ms_per_step=ms_launches, persistent_ms_per_step=ms_persistent,

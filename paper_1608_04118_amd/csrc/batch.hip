@@ -159,7 +159,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(
 
 // Two steps of every lattice (FP32 form) in one launch: wavefront w runs
 // strip and chunk w - wave_begin of lattice wave_cav[w], as the
-// single-lattice two-step kernel does.
+// single-lattice two-step kernel does; with kMacros in F the second step
+// also writes each lattice's macros.
 template <int F>
 __global__ __launch_bounds__(kBatch2Block) void batch2_kernel(char* base, const CavityDesc<float>* __restrict__ cav,
                                                         const StepConsts<float>* __restrict__ ks,
@@ -189,8 +190,9 @@ __global__ __launch_bounds__(kBatch2Block) void batch2_kernel(char* base, const 
   const CavityDesc<float>& d = cav[c];
   const int local = wave - d.wave_begin;
   const int nstrips = (k.nx + step2_out(k.px) - 1) / step2_out(k.px);
+  float* mac = (F & kMacros) ? at_offset<float>(base, d.mac) : nullptr;
   step2_wave<F>(at_offset<const float>(base, d.pop[parity]), at_offset<float>(base, d.pop[parity ^ 1]),
-                at_offset<const float>(base, d.phi), at_offset<const float>(base, d.hv), k,
+                at_offset<const float>(base, d.phi), at_offset<const float>(base, d.hv), mac, k,
                 kts[wl], local % nstrips, local / nstrips, d.rows2, step);
 }
 
@@ -252,8 +254,8 @@ __global__ __launch_bounds__(kPersistBlock) void batch2p_kernel(
       const int local = w - d.wave_begin;
       const int nstrips = (k.nx + step2_out(k.px) - 1) / step2_out(k.px);
       step2_wave<F>(at_offset<const float>(base, d.pop[parity]), at_offset<float>(base, d.pop[parity ^ 1]),
-                    at_offset<const float>(base, d.phi), at_offset<const float>(base, d.hv), k, kts[wl],
-                    local % nstrips, local / nstrips, d.rows2, step0 + 2u * static_cast<uint32_t>(s));
+                    at_offset<const float>(base, d.phi), at_offset<const float>(base, d.hv), nullptr, k,
+                    kts[wl], local % nstrips, local / nstrips, d.rows2, step0 + 2u * static_cast<uint32_t>(s));
       __builtin_amdgcn_wave_barrier();
     }
     if (s + 1 < npairs && !grid_barrier(ctl, gridDim.x, gen, spin_limit)) return;
@@ -389,29 +391,30 @@ int resident_grid(const lbm_ltne_batch* b, int* out, const void* fn = nullptr, i
 
 constexpr unsigned kSpinLimit = 1u << 24;
 
-hipError_t launch_batch2(const lbm_ltne_batch* b, int parity, uint32_t step) {
+template <int F>
+void launch_batch2_f(const lbm_ltne_batch* b, int parity, uint32_t step, bool macros) {
   const CavityDesc<float>* cav = reinterpret_cast<const CavityDesc<float>*>(b->base + b->off_cav);
   const StepConsts<float>* ks = reinterpret_cast<const StepConsts<float>*>(b->base + b->off_consts);
   const int* waves = reinterpret_cast<const int*>(b->base + b->off_waves);
   const int nblocks = (b->nwaves2 + kBatch2Block / 64 - 1) / (kBatch2Block / 64);
   const int per_xcd = (nblocks + kXcds - 1) / kXcds;
   const dim3 grid(kXcds * per_xcd), block(kBatch2Block);
+  if (macros)
+    hipLaunchKernelGGL(batch2_kernel<F | kMacros>, grid, block, 0, b->stream, b->base, cav, ks, waves, b->nwaves2,
+                       per_xcd, parity, step);
+  else
+    hipLaunchKernelGGL(batch2_kernel<F>, grid, block, 0, b->stream, b->base, cav, ks, waves, b->nwaves2, per_xcd,
+                       parity, step);
+}
+
+// A two-step launch over every lattice; macros: the second step also writes
+// the macros.
+hipError_t launch_batch2(const lbm_ltne_batch* b, int parity, uint32_t step, bool macros = false) {
   switch (b->fields) {
-    case kPhiField:
-      hipLaunchKernelGGL(batch2_kernel<kPhiField>, grid, block, 0, b->stream, b->base, cav, ks, waves, b->nwaves2, per_xcd,
-                         parity, step);
-      break;
-    case kHvField:
-      hipLaunchKernelGGL(batch2_kernel<kHvField>, grid, block, 0, b->stream, b->base, cav, ks, waves, b->nwaves2, per_xcd,
-                         parity, step);
-      break;
-    case kPhiField | kHvField:
-      hipLaunchKernelGGL(batch2_kernel<kPhiField | kHvField>, grid, block, 0, b->stream, b->base, cav, ks, waves, b->nwaves2,
-                         per_xcd, parity, step);
-      break;
-    default:
-      hipLaunchKernelGGL(batch2_kernel<0>, grid, block, 0, b->stream, b->base, cav, ks, waves, b->nwaves2, per_xcd, parity,
-                         step);
+    case kPhiField: launch_batch2_f<kPhiField>(b, parity, step, macros); break;
+    case kHvField: launch_batch2_f<kHvField>(b, parity, step, macros); break;
+    case kPhiField | kHvField: launch_batch2_f<kPhiField | kHvField>(b, parity, step, macros); break;
+    default: launch_batch2_f<0>(b, parity, step, macros);
   }
   return hipGetLastError();
 }
@@ -423,9 +426,10 @@ bool two_step_ok(const lbm_ltne_batch* b) {
 }
 
 // nsteps steps of every lattice.  Per-step mode: the FP32 form runs pairs
-// of steps in one two-step launch (two_step, and enough wavefronts) except
-// for a last step that writes the macros; the autotuner times single steps
-// only (the tile widths it chooses apply to them).
+// of steps in one two-step launch (two_step, and enough wavefronts), an odd
+// last step alone; the last launch writes the macros (macros_last).  The
+// autotuner's tile trials run single steps only (the tile widths it chooses
+// apply to them).
 int launch_batch(lbm_ltne_batch* b, int nsteps, int macros_last, bool two_step = true) {
   const void* fn = batch_function(b);
   char* base = b->base;
@@ -472,12 +476,12 @@ int launch_batch(lbm_ltne_batch* b, int nsteps, int macros_last, bool two_step =
     const int per = (ntiles + kXcds - 1) / kXcds;
     const int grid = kXcds * per;  // one tile per workgroup per step
     const bool two = two_ok;
-    const int last_single = macros_last ? 1 : 0;
     int parity = b->parity;
     for (int s = 0; s < nsteps;) {
       const uint32_t step0 = static_cast<uint32_t>(b->steps + 1 + s);
-      if (two && s + 2 <= nsteps - last_single) {
-        HIP_TRY(launch_batch2(b, parity, step0));
+      if (two && s + 2 <= nsteps) {
+        // the pair that ends the call writes the macros of its second step
+        HIP_TRY(launch_batch2(b, parity, step0, macros_last && s + 2 == nsteps));
         s += 2;
       } else {
         int one = 1;

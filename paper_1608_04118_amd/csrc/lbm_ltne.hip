@@ -156,27 +156,30 @@ Step2Map step2_map(const lbm_ltne_params& p) {
   return m;
 }
 
-// Two steps of the FP32 form in one launch (no macro output).
-hipError_t launch_step2(const lbm_ltne* h, int64_t step, const void* src, void* dst) {
-  const Step2Map m = step2_map(h->p);
+// Two steps of the FP32 form in one launch; with mac, the second step also
+// writes the macros (the last two steps of a call).
+template <int F>
+void launch_step2_f(const lbm_ltne* h, const Step2Map& m, const float* s, float* d, float* mac, uint32_t st) {
   const dim3 grid(kXcds * m.per_xcd), block(kStep2Block);
+  const float* phi = static_cast<const float*>(h->phi());
+  const float* hv = static_cast<const float*>(h->hv());
+  if (mac)
+    hipLaunchKernelGGL(step2_kernel<F | kMacros>, grid, block, 0, h->stream, s, d, phi, hv, mac, h->kf, m, st);
+  else
+    hipLaunchKernelGGL(step2_kernel<F>, grid, block, 0, h->stream, s, d, phi, hv, mac, h->kf, m, st);
+}
+
+hipError_t launch_step2(const lbm_ltne* h, int64_t step, const void* src, void* dst, void* mac = nullptr) {
+  const Step2Map m = step2_map(h->p);
   const uint32_t st = static_cast<uint32_t>(step);
   const float* s = static_cast<const float*>(src);
   float* d = static_cast<float*>(dst);
-  const float* phi = static_cast<const float*>(h->phi());
-  const float* hv = static_cast<const float*>(h->hv());
-  const int fl = (h->has_phi ? kPhiField : 0) | (h->has_hv ? kHvField : 0);
-  switch (fl) {
-    case 0: hipLaunchKernelGGL(step2_kernel<0>, grid, block, 0, h->stream, s, d, phi, hv, h->kf, m, st); break;
-    case kPhiField:
-      hipLaunchKernelGGL(step2_kernel<kPhiField>, grid, block, 0, h->stream, s, d, phi, hv, h->kf, m, st);
-      break;
-    case kHvField:
-      hipLaunchKernelGGL(step2_kernel<kHvField>, grid, block, 0, h->stream, s, d, phi, hv, h->kf, m, st);
-      break;
-    default:
-      hipLaunchKernelGGL(step2_kernel<kPhiField | kHvField>, grid, block, 0, h->stream, s, d, phi, hv, h->kf, m,
-                         st);
+  float* mc = static_cast<float*>(mac);
+  switch ((h->has_phi ? kPhiField : 0) | (h->has_hv ? kHvField : 0)) {
+    case 0: launch_step2_f<0>(h, m, s, d, mc, st); break;
+    case kPhiField: launch_step2_f<kPhiField>(h, m, s, d, mc, st); break;
+    case kHvField: launch_step2_f<kHvField>(h, m, s, d, mc, st); break;
+    default: launch_step2_f<kPhiField | kHvField>(h, m, s, d, mc, st);
   }
   return hipGetLastError();
 }
@@ -487,10 +490,11 @@ int lbm_ltne_step(lbm_ltne_t h, int64_t nsteps) {
   }
   while (s < nsteps) {
     const int64_t t = h->steps + 1;  // number of the next step
-    // a pair of steps in one launch while more than the last step (which
-    // also writes the macros) remains and neither step is checked
-    if (pairs && s + 2 <= nsteps - 1 && !checked(t) && !checked(t + 1)) {
-      hipError_t e = launch_step2(h, t, h->pop(h->cur), h->pop(1 - h->cur));
+    // a pair of steps in one launch where neither step is checked; the
+    // pair that ends the call also writes the macros of its second step
+    if (pairs && s + 2 <= nsteps && !checked(t) && !checked(t + 1)) {
+      const bool ends = s + 2 == nsteps;
+      hipError_t e = launch_step2(h, t, h->pop(h->cur), h->pop(1 - h->cur), ends ? scratch_mac : nullptr);
       if (e != hipSuccess) return set_error(LBM_EHIP, "step launch: %s", hipGetErrorString(e));
       h->cur = 1 - h->cur;
       h->steps += 2;

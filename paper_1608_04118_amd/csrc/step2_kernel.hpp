@@ -250,17 +250,21 @@ struct Step2Lane {
   float* __restrict__ dst;
   const float* __restrict__ phi_field;
   const float* __restrict__ hv_field;
+  float* __restrict__ mac;  // macros of the second step (F & kMacros)
   const StepConsts<float>& k;
   const ThermalK<double>& kt;
   uint32_t step;
   int lane, col, xo, dx, y_lo, y_hi;
   bool colok, outlane;
+  // the intermediate level writes no macros
+  static constexpr int FA = F & ~kMacros;
 
   __device__ __forceinline__ Step2Lane(const float* __restrict__ src_, float* __restrict__ dst_,
                                        const float* __restrict__ phi_, const float* __restrict__ hv_,
-                                       const StepConsts<float>& k_, const ThermalK<double>& kt_, const int strip,
-                                       const int chunk, const int rows, const uint32_t step_)
-      : src(src_), dst(dst_), phi_field(phi_), hv_field(hv_), k(k_), kt(kt_), step(step_) {
+                                       float* __restrict__ mac_, const StepConsts<float>& k_,
+                                       const ThermalK<double>& kt_, const int strip, const int chunk, const int rows,
+                                       const uint32_t step_)
+      : src(src_), dst(dst_), phi_field(phi_), hv_field(hv_), mac(mac_), k(k_), kt(kt_), step(step_) {
     lane = static_cast<int>(threadIdx.x) & 63;
     const int nx = k.nx, ny = k.ny;
     const int halo = step2_halo(k.px), out = step2_out(k.px);
@@ -320,7 +324,7 @@ struct Step2Lane {
     if (ok) {
       const RegPull<float> rp{v};
       RegPut<float> put{w};
-      node_update_with<float, float, F>(col, r, rp, put, phi_field, hv_field, nullptr, nullptr, nullptr, k, step,
+      node_update_with<float, float, FA>(col, r, rp, put, phi_field, hv_field, nullptr, nullptr, nullptr, k, step,
                                         nullptr, kt, &cf);
     } else {
 #pragma unroll
@@ -339,7 +343,7 @@ struct Step2Lane {
 #pragma nounroll
     for (int rep = 0; rep < nrep; ++rep) {
       const int yy = rep == 0 ? y : (y == 1 ? 0 : ny - 1);
-      node_update_with<float, float, F>(xo, yy, rpull, put, phi_field, hv_field, nullptr, nullptr, nullptr, k,
+      node_update_with<float, float, F>(xo, yy, rpull, put, phi_field, hv_field, mac, nullptr, nullptr, k,
                                         step + 1u, nullptr, kt, &fy);
     }
   }
@@ -352,13 +356,14 @@ struct Step2Lane {
 //      offsets by cross-lane permutes;
 //   3. updates the node at row y to time t + 2 and stores it.
 // kt: the lattice's temperature constants, a copy in LDS (see the kernels).
+// mac: the macros of the second step (F & kMacros), else unused.
 template <int F>
 __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float* __restrict__ dst,
                                            const float* __restrict__ phi_field, const float* __restrict__ hv_field,
-                                           const StepConsts<float>& k, const ThermalK<double>& kt,
-                                           const int strip, const int chunk, const int rows,
-                                           const uint32_t step) {
-  const Step2Lane<F> L(src, dst, phi_field, hv_field, k, kt, strip, chunk, rows, step);
+                                           float* __restrict__ mac, const StepConsts<float>& k,
+                                           const ThermalK<double>& kt, const int strip, const int chunk,
+                                           const int rows, const uint32_t step) {
+  const Step2Lane<F> L(src, dst, phi_field, hv_field, mac, k, kt, strip, chunk, rows, step);
   const int y_lo = L.y_lo, y_hi = L.y_hi, lane = L.lane, dx = L.dx;
   if (y_lo >= y_hi) return;
 
@@ -402,8 +407,8 @@ template <int F>
 __global__ __launch_bounds__(kStep2Block) void step2_kernel(const float* __restrict__ src, float* __restrict__ dst,
                                                        const float* __restrict__ phi_field,
                                                        const float* __restrict__ hv_field,
-                                                       const StepConsts<float> k, const Step2Map m,
-                                                       const uint32_t step) {
+                                                       float* __restrict__ mac, const StepConsts<float> k,
+                                                       const Step2Map m, const uint32_t step) {
   const int b = blockIdx.x;
   const int blk = (b & (kXcds - 1)) * m.per_xcd + (b >> 3);
   const int wave = blk * (kStep2Block / 64) + (static_cast<int>(threadIdx.x) >> 6);
@@ -413,7 +418,7 @@ __global__ __launch_bounds__(kStep2Block) void step2_kernel(const float* __restr
   copy_to_lds(k.td, kt);
   __syncthreads();
   if (wave >= m.nwaves) return;  // whole wavefronts
-  step2_wave<F>(src, dst, phi_field, hv_field, k, kt, wave % m.nstrips, wave / m.nstrips, m.rows, step);
+  step2_wave<F>(src, dst, phi_field, hv_field, mac, k, kt, wave % m.nstrips, wave / m.nstrips, m.rows, step);
 }
 
 }  // namespace ltne
