@@ -115,8 +115,9 @@ CUS, CLOCK_HZ = 256, 2.4e9
 VALU_ISSUE_PER_S = CUS * CLOCK_HZ
 
 
-# Forms whose steps run two to a launch (an odd last step of a call alone)
-TWO_STEP = ("f32", "f32ext")
+# Forms whose steps run two to a launch on the 8192^2 layer (an odd last step
+# of a call alone)
+TWO_STEP = ("f32", "f32ext", "f64")
 
 
 def _events_ms(stream, fn):
@@ -276,6 +277,12 @@ def copy_bandwidth(gib: float = 1.0, reps: int = 5):
     return {"bytes_read": n * 4, "bytes_written": n * 4, "ms": ms, "gbs": 2 * n * 4 / ms / 1e6}
 
 
+def is_head_kernel(name: str) -> bool:
+    """The FP32 two-step kernel with the porosity field (the 8192^2 layer's),
+    by its demangled or mangled name in a rocprofv3 record."""
+    return "step2_kernel<float, 1>" in name or "step2_kernelIfLi1E" in name
+
+
 def ingest_counters(fetch_csv: str, write_csv: str, copy_bytes: int, out_path: str):
     """Turns two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per
     dispatch) of `bench.py --forms f32 --copy-check` into HBM bytes per
@@ -298,8 +305,7 @@ def ingest_counters(fetch_csv: str, write_csv: str, copy_bytes: int, out_path: s
         vals = per_kernel(path, counter)
         copy = [v for k, vs in vals.items() if "copy" in k.lower()
                 for v in vs if v * 1024 > 0.25 * copy_bytes]
-        step = [v for k, vs in vals.items()
-                if "step2_kernel" in k and ("<1>" in k or "ILi1E" in k) for v in vs]
+        step = [v for k, vs in vals.items() if is_head_kernel(k) for v in vs]
         if not copy or not step:
             raise SystemExit("counters for the copy or the step kernel not found in %s" % path)
         scale = copy_bytes / (np.median(copy) * 1024.0)
@@ -323,7 +329,7 @@ def ingest_sq(csv_path: str, out_path: str):
     vals = {}
     for row in csv.DictReader(open(csv_path)):
         k = row["Kernel_Name"]
-        if "step2_kernel" in k and ("<1>" in k or "ILi1E" in k):
+        if is_head_kernel(k):
             vals.setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
     if "SQ_INSTS_VALU" not in vals:
         raise SystemExit("SQ_INSTS_VALU of the two-step kernel not found in %s" % csv_path)
@@ -526,7 +532,7 @@ def roofline(head: str, r: dict, traffic):
            "bytes_per_launch": must, "launch_ms": round(r["launch_ms"], 4)}
     if r["steps_per_launch"] == 2:
         eq = must * 2 / launch_s / 1e9
-        out["kernel"] = ("step2_kernel<kPhiField>: two time steps per launch over %d^2 nodes; %d B per node "
+        out["kernel"] = ("step2_kernel<float, kPhiField>: two time steps per launch over %d^2 nodes; %d B per node "
                          "per launch (state read and written once)" % (N, BYTES_PER_LUP[head]))
         out["one_step_equivalent"] = {"bytes_per_launch": must * 2, "gbs": round(eq, 1),
                                       "frac": round(eq / HBM_PEAK_GBS, 4)}

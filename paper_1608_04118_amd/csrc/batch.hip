@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kBatch2Block) void batch2_kernel(char* base, const 
   const int local = wave - d.wave_begin;
   const int nstrips = (k.nx + step2_out(k.px) - 1) / step2_out(k.px);
   float* mac = (F & kMacros) ? at_offset<float>(base, d.mac) : nullptr;
-  step2_wave<F>(at_offset<const float>(base, d.pop[parity]), at_offset<float>(base, d.pop[parity ^ 1]),
+  step2_wave<F, float>(at_offset<const float>(base, d.pop[parity]), at_offset<float>(base, d.pop[parity ^ 1]),
                 at_offset<const float>(base, d.phi), at_offset<const float>(base, d.hv), mac, k,
                 kts[wl], local % nstrips, local / nstrips, d.rows2, step);
 }
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kPersistBlock) void batch2p_kernel(
       const CavityDesc<float>& d = cav[c];
       const int local = w - d.wave_begin;
       const int nstrips = (k.nx + step2_out(k.px) - 1) / step2_out(k.px);
-      step2_wave<F>(at_offset<const float>(base, d.pop[parity]), at_offset<float>(base, d.pop[parity ^ 1]),
+      step2_wave<F, float>(at_offset<const float>(base, d.pop[parity]), at_offset<float>(base, d.pop[parity ^ 1]),
                     at_offset<const float>(base, d.phi), at_offset<const float>(base, d.hv), nullptr, k,
                     kts[wl], local % nstrips, local / nstrips, d.rows2, step0 + 2u * static_cast<uint32_t>(s));
       __builtin_amdgcn_wave_barrier();
@@ -632,7 +632,7 @@ int lbm_ltne_batch_create(int32_t n, const lbm_ltne_params* ps, const double* co
     for (int sh = 6; sh <= 8; ++sh) most = std::max(most, make_tiles(ps[i].nx, ps[i].ny, precision, sh).ntiles);
     b->max_tiles += most;
     b->nwaves2_min += step2_waves(ps[i].nx, ps[i].ny, ps[i].periodic_x, kStep2MinRows);
-    b->step2_addr = b->step2_addr && step2_addressable(ps[i].nx);
+    b->step2_addr = b->step2_addr && step2_addressable(ps[i].nx, sizeof(float));
   }
   const bool cdouble = compute_bytes(precision) == 8;
   b->consts_bytes = (cdouble ? sizeof(StepConsts<double>) : sizeof(StepConsts<float>));

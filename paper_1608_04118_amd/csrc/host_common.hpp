@@ -42,9 +42,9 @@ inline long long pop_row_elems(int nx) { return static_cast<long long>(align_up(
 inline long long pop_elems(int nx, int ny) { return kPlanes * pop_row_elems(nx) * ny; }
 // The two-step kernel addresses a lattice row (its kPlanes population rows)
 // through one buffer resource with 32-bit byte offsets: the row must span
-// less than 2^31 bytes of binary32 populations.
-inline bool step2_addressable(int nx) {
-  return kPlanes * pop_row_elems(nx) * static_cast<long long>(sizeof(float)) < (1LL << 31);
+// less than 2^31 bytes of populations (elem_bytes each).
+inline bool step2_addressable(int nx, size_t elem_bytes) {
+  return kPlanes * pop_row_elems(nx) * static_cast<long long>(elem_bytes) < (1LL << 31);
 }
 
 struct Layout {

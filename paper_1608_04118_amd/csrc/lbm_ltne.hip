@@ -156,31 +156,40 @@ Step2Map step2_map(const lbm_ltne_params& p) {
   return m;
 }
 
-// Two steps of the FP32 form in one launch; with mac, the second step also
-// writes the macros (the last two steps of a call).
-template <int F>
-void launch_step2_f(const lbm_ltne* h, const Step2Map& m, const float* s, float* d, float* mac, uint32_t st) {
+// Two steps in one launch (FP32 and FP64 forms); with mac, the second step
+// also writes the macros (the last two steps of a call).
+template <typename S, int F>
+void launch_step2_t(const lbm_ltne* h, const StepConsts<S>& k, const Step2Map& m, const S* s, S* d, S* mac,
+                    uint32_t st) {
   const dim3 grid(kXcds * m.per_xcd), block(kStep2Block);
-  const float* phi = static_cast<const float*>(h->phi());
-  const float* hv = static_cast<const float*>(h->hv());
+  const S* phi = static_cast<const S*>(h->phi());
+  const S* hv = static_cast<const S*>(h->hv());
   if (mac)
-    hipLaunchKernelGGL(step2_kernel<F | kMacros>, grid, block, 0, h->stream, s, d, phi, hv, mac, h->kf, m, st);
+    hipLaunchKernelGGL((step2_kernel<S, F | kMacros>), grid, block, 0, h->stream, s, d, phi, hv, mac, k, m, st);
   else
-    hipLaunchKernelGGL(step2_kernel<F>, grid, block, 0, h->stream, s, d, phi, hv, mac, h->kf, m, st);
+    hipLaunchKernelGGL((step2_kernel<S, F>), grid, block, 0, h->stream, s, d, phi, hv, mac, k, m, st);
+}
+
+template <typename S>
+void launch_step2_s(const lbm_ltne* h, const StepConsts<S>& k, uint32_t st, const void* src, void* dst, void* mac) {
+  const Step2Map m = step2_map(h->p);
+  const S* s = static_cast<const S*>(src);
+  S* d = static_cast<S*>(dst);
+  S* mc = static_cast<S*>(mac);
+  switch ((h->has_phi ? kPhiField : 0) | (h->has_hv ? kHvField : 0)) {
+    case 0: launch_step2_t<S, 0>(h, k, m, s, d, mc, st); break;
+    case kPhiField: launch_step2_t<S, kPhiField>(h, k, m, s, d, mc, st); break;
+    case kHvField: launch_step2_t<S, kHvField>(h, k, m, s, d, mc, st); break;
+    default: launch_step2_t<S, kPhiField | kHvField>(h, k, m, s, d, mc, st);
+  }
 }
 
 hipError_t launch_step2(const lbm_ltne* h, int64_t step, const void* src, void* dst, void* mac = nullptr) {
-  const Step2Map m = step2_map(h->p);
   const uint32_t st = static_cast<uint32_t>(step);
-  const float* s = static_cast<const float*>(src);
-  float* d = static_cast<float*>(dst);
-  float* mc = static_cast<float*>(mac);
-  switch ((h->has_phi ? kPhiField : 0) | (h->has_hv ? kHvField : 0)) {
-    case 0: launch_step2_f<0>(h, m, s, d, mc, st); break;
-    case kPhiField: launch_step2_f<kPhiField>(h, m, s, d, mc, st); break;
-    case kHvField: launch_step2_f<kHvField>(h, m, s, d, mc, st); break;
-    default: launch_step2_f<kPhiField | kHvField>(h, m, s, d, mc, st);
-  }
+  if (h->p.precision == LBM_FP64)
+    launch_step2_s<double>(h, h->kd, st, src, dst, mac);
+  else
+    launch_step2_s<float>(h, h->kf, st, src, dst, mac);
   return hipGetLastError();
 }
 
@@ -468,7 +477,8 @@ int lbm_ltne_step(lbm_ltne_t h, int64_t nsteps) {
   // two steps per launch where the lattice gives the two-step kernel enough
   // wavefronts to hide its latency (each wavefront runs a serial chain of
   // rows); small lattices run faster one step at a time
-  const bool pairs = h->p.precision == LBM_FP32 && step2_addressable(h->p.nx) &&
+  const bool pairs = (h->p.precision == LBM_FP32 || h->p.precision == LBM_FP64) &&
+                     step2_addressable(h->p.nx, storage_bytes(h->p.precision)) &&
                      step2_waves(h->p.nx, h->p.ny, h->p.periodic_x, kStep2MinRows) >= LTNE_STEP2_MIN_WAVES;
   const int64_t de = h->p.diag_every;
   auto checked = [de](int64_t t) { return de > 0 && t % de == 0; };

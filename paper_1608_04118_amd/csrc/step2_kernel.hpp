@@ -103,15 +103,34 @@ struct Step2Map {
 // resource per lattice row (its 19 population rows), the population's offset
 // in the scalar offset operand and the lane's column in the vector offset,
 // so no vector instruction is spent forming 64-bit addresses.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float* row, long long rs) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(row), static_cast<short>(0),
-                                           static_cast<int>(rs * static_cast<long long>(sizeof(float))),
-                                           0x00020000);
+template <typename S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const S* row, long long rs) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(row), static_cast<short>(0),
+                                           static_cast<int>(rs * static_cast<long long>(sizeof(S))), 0x00020000);
 }
 
+// One element (binary32 or binary64) through a buffer resource.
+template <typename S>
+__device__ __forceinline__ S buf_load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+  if constexpr (sizeof(S) == 8)
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+  else
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+template <int Aux, typename S>
+__device__ __forceinline__ void buf_store(S v, __amdgpu_buffer_rsrc_t r, int vo, int so) {
+  if constexpr (sizeof(S) == 8) {
+    using W = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(W, v), r, vo, so, Aux);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, vo, so, Aux);
+  }
+}
+
+template <typename S>
 struct BufPull {
-  const float* __restrict__ src;
-  __device__ __forceinline__ void operator()(int xc, int yc, const StepConsts<float>& k, float (&v)[kPlanes]) const {
+  const S* __restrict__ src;
+  __device__ __forceinline__ void operator()(int xc, int yc, const StepConsts<S>& k, S (&v)[kPlanes]) const {
     const int nx = k.nx, ny = k.ny;
     const int yu = __builtin_amdgcn_readfirstlane(yc);
     int xm = xc - 1, xp = xc + 1, ym = yu - 1, yp = yu + 1;
@@ -126,11 +145,10 @@ struct BufPull {
     const __amdgpu_buffer_rsrc_t r0 = row_rsrc(src + yu * k.rs, k.rs);
     const __amdgpu_buffer_rsrc_t rm = row_rsrc(src + ym * k.rs, k.rs);
     const __amdgpu_buffer_rsrc_t rp = row_rsrc(src + yp * k.rs, k.rs);
-    const int Q = static_cast<int>(k.qs) * 4;
-    const int oc = xc * 4, om = xm * 4, op = xp * 4;
-    auto ld = [&](__amdgpu_buffer_rsrc_t r, int vo, int q) {
-      return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, q * Q, 0));
-    };
+    constexpr int E = sizeof(S);
+    const int Q = static_cast<int>(k.qs) * E;
+    const int oc = xc * E, om = xm * E, op = xp * E;
+    auto ld = [&](__amdgpu_buffer_rsrc_t r, int vo, int q) { return buf_load<S>(r, vo, q * Q); };
     v[0] = ld(r0, oc, 0);
     v[1] = ld(r0, om, 1);
     v[2] = ld(rm, oc, 2);
@@ -155,42 +173,41 @@ struct BufPull {
 
 // One field value (porosity or H_v) of node (xc, yc) through a buffer
 // resource over the field's row, so a wavefront's loads are all of one kind.
-__device__ __forceinline__ float buf_field(const float* __restrict__ f, int xc, int yc, int nx) {
+template <typename S>
+__device__ __forceinline__ S buf_field(const S* __restrict__ f, int xc, int yc, int nx) {
   const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<float*>(f + static_cast<long long>(__builtin_amdgcn_readfirstlane(yc)) * nx), static_cast<short>(0),
-      nx * static_cast<int>(sizeof(float)), 0x00020000);
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, xc * 4, 0, 0));
+      const_cast<S*>(f + static_cast<long long>(__builtin_amdgcn_readfirstlane(yc)) * nx), static_cast<short>(0),
+      nx * static_cast<int>(sizeof(S)), 0x00020000);
+  return buf_load<S>(r, xc * static_cast<int>(sizeof(S)), 0);
 }
 
-template <int F>
-__device__ __forceinline__ CenterFields<float> buf_center(const float* __restrict__ phi_field,
-                                                          const float* __restrict__ hv_field, int xc, int yc,
-                                                          const StepConsts<float>& k) {
+template <int F, typename S>
+__device__ __forceinline__ CenterFields<S> buf_center(const S* __restrict__ phi_field, const S* __restrict__ hv_field,
+                                                      int xc, int yc, const StepConsts<S>& k) {
   return {(F & kPhiField) ? buf_field(phi_field, xc, yc, k.nx) : k.phi_u,
           (F & kHvField) ? buf_field(hv_field, xc, yc, k.nx) : k.hv_u};
 }
 
+template <typename S>
 struct BufPut {
   // cache policy of the stores: the non-temporal bit when kStep2NtStore
   static constexpr int kNtAux = kStep2NtStore ? 2 : 0;
-  float* __restrict__ dst;
+  S* __restrict__ dst;
   __amdgpu_buffer_rsrc_t r;
   int vo = 0, Q = 0;
-  __device__ __forceinline__ void begin(int x, int y, const StepConsts<float>& k) {
+  __device__ __forceinline__ void begin(int x, int y, const StepConsts<S>& k) {
     r = row_rsrc(dst + static_cast<long long>(__builtin_amdgcn_readfirstlane(y)) * k.rs, k.rs);
-    vo = x * 4;
-    Q = static_cast<int>(k.qs) * 4;
+    vo = x * static_cast<int>(sizeof(S));
+    Q = static_cast<int>(k.qs) * static_cast<int>(sizeof(S));
   }
-  __device__ __forceinline__ void st(int i, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, vo, i * Q, kNtAux);
-  }
+  __device__ __forceinline__ void st(int i, S v) { buf_store<kNtAux>(v, r, vo, i * Q); }
   template <typename VA, typename VB>
   __device__ __forceinline__ void pair(int i, VA va, VA, int j, VB vb, VB, uint32_t w, half2_t&) {
-    st(i, to_storage<float>(va, w << 16));
-    st(j, to_storage<float>(vb, w));
+    st(i, to_storage<S>(va, w << 16));
+    st(j, to_storage<S>(vb, w));
   }
   template <typename V>
-  __device__ __forceinline__ void single(int i, V v, V, uint32_t w) { st(i, to_storage<float>(v, w)); }
+  __device__ __forceinline__ void single(int i, V v, V, uint32_t w) { st(i, to_storage<S>(v, w)); }
 };
 
 // Copies a constant block into LDS, one 8-byte word per thread.
@@ -235,8 +252,8 @@ struct RegPull {
 // at the end of the row, and that copy waits for every memory access issued
 // before it, stores included.  Uniform fields (not loaded) are left as they
 // are, so that what derives from them stays hoisted out of the row loop.
-template <int F>
-__device__ __forceinline__ CenterFields<float> detach(CenterFields<float> f) {
+template <int F, typename S>
+__device__ __forceinline__ CenterFields<S> detach(CenterFields<S> f) {
   if constexpr ((F & kPhiField) != 0) asm volatile("" : "+v"(f.phi));
   if constexpr ((F & kHvField) != 0) asm volatile("" : "+v"(f.hv));
   return f;
@@ -244,14 +261,14 @@ __device__ __forceinline__ CenterFields<float> detach(CenterFields<float> f) {
 
 // The work of one lane of a strip and chunk: its columns, the chunk's rows,
 // and the three parts of the update (fetch, intermediate level, output).
-template <int F>
+template <typename S, int F>
 struct Step2Lane {
-  const float* __restrict__ src;
-  float* __restrict__ dst;
-  const float* __restrict__ phi_field;
-  const float* __restrict__ hv_field;
-  float* __restrict__ mac;  // macros of the second step (F & kMacros)
-  const StepConsts<float>& k;
+  const S* __restrict__ src;
+  S* __restrict__ dst;
+  const S* __restrict__ phi_field;
+  const S* __restrict__ hv_field;
+  S* __restrict__ mac;  // macros of the second step (F & kMacros)
+  const StepConsts<S>& k;
   const ThermalK<double>& kt;
   uint32_t step;
   int lane, col, xo, dx, y_lo, y_hi;
@@ -259,9 +276,9 @@ struct Step2Lane {
   // the intermediate level writes no macros
   static constexpr int FA = F & ~kMacros;
 
-  __device__ __forceinline__ Step2Lane(const float* __restrict__ src_, float* __restrict__ dst_,
-                                       const float* __restrict__ phi_, const float* __restrict__ hv_,
-                                       float* __restrict__ mac_, const StepConsts<float>& k_,
+  __device__ __forceinline__ Step2Lane(const S* __restrict__ src_, S* __restrict__ dst_,
+                                       const S* __restrict__ phi_, const S* __restrict__ hv_,
+                                       S* __restrict__ mac_, const StepConsts<S>& k_,
                                        const ThermalK<double>& kt_, const int strip, const int chunk, const int rows,
                                        const uint32_t step_)
       : src(src_), dst(dst_), phi_field(phi_), hv_field(hv_), mac(mac_), k(k_), kt(kt_), step(step_) {
@@ -302,14 +319,14 @@ struct Step2Lane {
   // the pulls of node (col, r) at time t (a wall node pulls those of its
   // inward neighbour) and the porosity and H_v there, issued ahead of their
   // use so the loads overlap arithmetic
-  __device__ __forceinline__ void fetch(int r, float (&v)[kPlanes], CenterFields<float>& cf) const {
+  __device__ __forceinline__ void fetch(int r, S (&v)[kPlanes], CenterFields<S>& cf) const {
     bool ok;
     r = row_of(r, ok);
     if (ok) {
       const int nx = k.nx, ny = k.ny;
       const int xc = (!k.px && col == 0) ? 1 : ((!k.px && col == nx - 1) ? nx - 2 : col);
       const int yc = (!k.py && r == 0) ? 1 : ((!k.py && r == ny - 1) ? ny - 2 : r);
-      const BufPull gpull{src};
+      const BufPull<S> gpull{src};
       gpull(xc, yc, k, v);
       cf = buf_center<F>(phi_field, hv_field, xc, yc, k);
     }
@@ -317,33 +334,33 @@ struct Step2Lane {
 
   // node (col, r) at time t + 1 from its fetched pulls and fields into w;
   // zeros where there is no node
-  __device__ __forceinline__ void advance(int r, const float (&v)[kPlanes], const CenterFields<float>& cf,
-                                          float (&w)[kPlanes]) const {
+  __device__ __forceinline__ void advance(int r, const S (&v)[kPlanes], const CenterFields<S>& cf,
+                                          S (&w)[kPlanes]) const {
     bool ok;
     r = row_of(r, ok);
     if (ok) {
-      const RegPull<float> rp{v};
-      RegPut<float> put{w};
-      node_update_with<float, float, FA>(col, r, rp, put, phi_field, hv_field, nullptr, nullptr, nullptr, k, step,
+      const RegPull<S> rp{v};
+      RegPut<S> put{w};
+      node_update_with<S, S, FA>(col, r, rp, put, phi_field, hv_field, nullptr, nullptr, nullptr, k, step,
                                         nullptr, kt, &cf);
     } else {
 #pragma unroll
-      for (int i = 0; i < kPlanes; ++i) w[i] = 0.0f;
+      for (int i = 0; i < kPlanes; ++i) w[i] = S(0);
     }
   }
 
   // node (xo, y) at time t + 2 from its gathered pulls g (time t + 1) and the
   // fields fy of its pulled node, stored; then the wall row it feeds (one
   // call site)
-  __device__ __forceinline__ void output(int y, const float (&g)[kPlanes], const CenterFields<float>& fy) const {
-    const RegPull<float> rpull{g};
-    BufPut put{dst};
+  __device__ __forceinline__ void output(int y, const S (&g)[kPlanes], const CenterFields<S>& fy) const {
+    const RegPull<S> rpull{g};
+    BufPut<S> put{dst};
     const int ny = k.ny;
     const int nrep = (!k.py && (y == 1 || y == ny - 2)) ? 2 : 1;
 #pragma nounroll
     for (int rep = 0; rep < nrep; ++rep) {
       const int yy = rep == 0 ? y : (y == 1 ? 0 : ny - 1);
-      node_update_with<float, float, F>(xo, yy, rpull, put, phi_field, hv_field, mac, nullptr, nullptr, k,
+      node_update_with<S, S, F>(xo, yy, rpull, put, phi_field, hv_field, mac, nullptr, nullptr, k,
                                         step + 1u, nullptr, kt, &fy);
     }
   }
@@ -357,19 +374,19 @@ struct Step2Lane {
 //   3. updates the node at row y to time t + 2 and stores it.
 // kt: the lattice's temperature constants, a copy in LDS (see the kernels).
 // mac: the macros of the second step (F & kMacros), else unused.
-template <int F>
-__device__ __forceinline__ void step2_wave(const float* __restrict__ src, float* __restrict__ dst,
-                                           const float* __restrict__ phi_field, const float* __restrict__ hv_field,
-                                           float* __restrict__ mac, const StepConsts<float>& k,
+template <int F, typename S>
+__device__ __forceinline__ void step2_wave(const S* __restrict__ src, S* __restrict__ dst,
+                                           const S* __restrict__ phi_field, const S* __restrict__ hv_field,
+                                           S* __restrict__ mac, const StepConsts<S>& k,
                                            const ThermalK<double>& kt, const int strip, const int chunk,
                                            const int rows, const uint32_t step) {
-  const Step2Lane<F> L(src, dst, phi_field, hv_field, mac, k, kt, strip, chunk, rows, step);
+  const Step2Lane<S, F> L(src, dst, phi_field, hv_field, mac, k, kt, strip, chunk, rows, step);
   const int y_lo = L.y_lo, y_hi = L.y_hi, lane = L.lane, dx = L.dx;
   if (y_lo >= y_hi) return;
 
-  float wa[kPlanes], wb[kPlanes], wc[kPlanes];  // time t + 1 at rows y - 1, y, y + 1
-  float pa[kPlanes], pb[kPlanes];               // fetched pulls of two rows
-  CenterFields<float> fa{}, fb{};               // and the fields fetched with them
+  S wa[kPlanes], wb[kPlanes], wc[kPlanes];  // time t + 1 at rows y - 1, y, y + 1
+  S pa[kPlanes], pb[kPlanes];               // fetched pulls of two rows
+  CenterFields<S> fa{}, fb{};               // and the fields fetched with them
   L.fetch(y_lo - 1, pa, fa);
   L.fetch(y_lo, pb, fb);
   L.advance(y_lo - 1, pa, fa, wa);
@@ -377,19 +394,19 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
   L.advance(y_lo, pb, fb, wb);
   // fields of node (col, y), the pulled node of the output update at row y
   // (on an output lane col = xo, and a wall row pulls from row y as well)
-  CenterFields<float> fy = detach<F>(fb);
+  CenterFields<S> fy = detach<F>(fb);
 #pragma nounroll
   for (int y = y_lo; y < y_hi; ++y) {
     L.advance(y + 1, pa, fa, wc);
-    const CenterFields<float> fn = detach<F>(fa);
+    const CenterFields<S> fn = detach<F>(fa);
     if (y + 1 < y_hi) L.fetch(y + 2, pa, fa);
     // pulls of node (xo + dx, y) at time t + 1: population i from column
     // xo + dx - e_ix (lane offset) and row y - e_iy (window row)
-    float g[kPlanes];
+    S g[kPlanes];
 #pragma unroll
     for (int i = 0; i < kPlanes; ++i) {
       const int q = i < 9 ? i : (i < 14 ? i - 9 : i - 14);
-      const float v = vel_y(q) == 1 ? wa[i] : (vel_y(q) == -1 ? wc[i] : wb[i]);
+      const S v = vel_y(q) == 1 ? wa[i] : (vel_y(q) == -1 ? wc[i] : wb[i]);
       const int sl = (lane + dx - vel_x(q)) & 63;
       g[i] = __shfl(v, sl, 64);
     }
@@ -403,11 +420,11 @@ __device__ __forceinline__ void step2_wave(const float* __restrict__ src, float*
   }
 }
 
-template <int F>
-__global__ __launch_bounds__(kStep2Block) void step2_kernel(const float* __restrict__ src, float* __restrict__ dst,
-                                                       const float* __restrict__ phi_field,
-                                                       const float* __restrict__ hv_field,
-                                                       float* __restrict__ mac, const StepConsts<float> k,
+template <typename S, int F>
+__global__ __launch_bounds__(kStep2Block) void step2_kernel(const S* __restrict__ src, S* __restrict__ dst,
+                                                       const S* __restrict__ phi_field,
+                                                       const S* __restrict__ hv_field,
+                                                       S* __restrict__ mac, const StepConsts<S> k,
                                                        const Step2Map m, const uint32_t step) {
   const int b = blockIdx.x;
   const int blk = (b & (kXcds - 1)) * m.per_xcd + (b >> 3);

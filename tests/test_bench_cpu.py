@@ -66,7 +66,7 @@ def _counter_csv(path, counter, rows):
 
 
 def test_ingest_counters_calibrates_by_the_copy(tmp_path, capsys):
-    copy, step2, other = "__amd_rocclr_copyBuffer", "void ltne::step2_kernel<1>(float const*, ...)", \
+    copy, step2, other = "__amd_rocclr_copyBuffer", "void ltne::step2_kernel<float, 1>(float const*, ...)", \
         "void ltne::step_kernel<float, float, 5>(...)"
     gib = 2 ** 30
     # FETCH_SIZE reads half the copy's bytes (scale 2), WRITE_SIZE all of them
@@ -110,7 +110,7 @@ def test_sq_ingest_and_roofline_block(tmp_path, monkeypatch):
         w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
         w.writeheader()
         for v in (1.0e9, 1.2e9, 1.1e9):
-            w.writerow({"Kernel_Name": "void ltne::step2_kernel<1>(float const*, ...)",
+            w.writerow({"Kernel_Name": "void ltne::step2_kernel<float, 1>(float const*, ...)",
                         "Counter_Name": "SQ_INSTS_VALU", "Counter_Value": v})
         w.writerow({"Kernel_Name": "void ltne::step_kernel<float, float, 5>(...)",
                     "Counter_Name": "SQ_INSTS_VALU", "Counter_Value": 5.0})

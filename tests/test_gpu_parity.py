@@ -307,16 +307,26 @@ TWO_STEP_CASES = [
                                                 None, None, None)),
     ("layer 6000x5000, tall chunks", lambda: I.throughput(n=6000, ny=5000)),
     ("layer 8192x8192, tall chunks", lambda: I.throughput(n=8192)),
+    # the FP64 form
+    ("fp64 layer 1100x1027, phi field", lambda: I.throughput(n=1100, ny=1027, precision=I.FP64)),
+    ("fp64 cavity 1038x1030", lambda: (I.cavity_small(nx=1038, ny=1030, Ra=1e5), None, None, None)),
+    ("fp64 torus 1030x1030", lambda: (I.complete(nx=1030, ny=1030, periodic_x=1, periodic_y=1, precision=I.FP64,
+                                                 Ra=1e4, body_force=(1e-4, -2e-5)), None, None, None)),
+    ("fp64 cavity 1024x1024, both extensions", lambda: (I.cavity_small(nx=1024, ny=1024, Ra=1e5,
+                                                                       thermal_correction=1, pore_size=0.0135),
+                                                        None, None, None)),
+    ("fp64 layer 8192x8192, tall chunks", lambda: I.throughput(n=8192, precision=I.FP64)),
 ]
 
 
 @pytest.mark.parametrize("nsteps", [41, 40], ids=["odd", "even"])
 @pytest.mark.parametrize("case", TWO_STEP_CASES, ids=[c[0] for c in TWO_STEP_CASES])
 def test_two_step_launch_equals_single_steps(B, case, nsteps):
-    """The FP32 form advances pairs of steps in one launch on lattices this
-    size (an odd call ends with one single step, which writes the macros; in
-    an even call the last pair writes them); the result equals single steps
-    bit for bit: nsteps steps in one call against nsteps calls of one step."""
+    """The FP32 and FP64 forms advance pairs of steps in one launch on
+    lattices this size (an odd call ends with one single step, which writes
+    the macros; in an even call the last pair writes them); the result equals
+    single steps bit for bit: nsteps steps in one call against nsteps calls of
+    one step."""
     name, make = case
     p, phi, Tf0, Ts0 = make()
     a = B.Lattice(p, phi=phi, Tf0=Tf0, Ts0=Ts0).step(nsteps)
