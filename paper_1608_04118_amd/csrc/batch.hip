@@ -741,7 +741,7 @@ int lbm_ltne_batch_set_chunks(lbm_ltne_batch_t b, const int32_t* rows) {
   if (!b || !rows) return set_error(LBM_EINVAL, "batch or chunk heights NULL");
   for (int i = 0; i < b->n; ++i) {
     bool ok = rows[i] == 0;
-    for (int r : kStep2RowChoices) ok = ok || rows[i] == r;
+    for (int r : kBatch2RowChoices) ok = ok || rows[i] == r;
     if (!ok) return set_error(LBM_EINVAL, "chunk height %d of lattice %d not in {0, 8, 12, 16, 24, 32}", rows[i], i);
   }
   for (int i = 0; i < b->n; ++i) b->rows2[i] = rows[i] ? rows[i] : kBatch2Rows;
@@ -852,7 +852,7 @@ int lbm_ltne_batch_autotune(lbm_ltne_batch_t b, int32_t reps, double* ms_per_ste
     for (auto& kv : classes) {
       if (rc != LBM_OK) break;
       int best_rows = b->rows2[kv.second[0]];
-      for (int r : kStep2RowChoices) {
+      for (int r : kBatch2RowChoices) {
         if (r == best_rows) continue;
         for (int i : kv.second) b->rows2[i] = r;
         rc = upload_tables(b);

@@ -148,7 +148,7 @@ Step2Map step2_map(const lbm_ltne_params& p) {
   m.halo = step2_halo(p.periodic_x);
   m.out = step2_out(p.periodic_x);
   m.nstrips = (p.nx + m.out - 1) / m.out;
-  m.rows = step2_rows(p.nx, p.ny, p.periodic_x);
+  m.rows = step2_rows(p.nx, p.ny, p.periodic_x, storage_bytes(p.precision));
   m.nchunks = (p.ny + m.rows - 1) / m.rows;
   m.nwaves = m.nstrips * m.nchunks;
   const int nblocks = (m.nwaves + kStep2Block / 64 - 1) / (kStep2Block / 64);

@@ -27,9 +27,15 @@ namespace ltne {
 // level, so taller chunks do less redundant work but leave fewer wavefronts
 // in flight.  A single lattice takes the tallest of kStep2RowChoices that
 // still yields kStep2TargetWaves wavefronts; a batch of lattices (many small
-// ones) uses kBatch2Rows.  LTNE_STEP2_ROWS forces one height (experiments).
-constexpr int kStep2RowChoices[] = {32, 24, 16, 12, 8};
+// ones) uses kBatch2Rows.  The binary64 kernel holds one wavefront per SIMD
+// (it needs more than half the register file), so it fills the chip with
+// half the wavefronts and may take chunks of 64 rows.  LTNE_STEP2_ROWS
+// forces one height (experiments).
+constexpr int kStep2RowChoices[] = {64, 32, 24, 16, 12, 8};
+constexpr int kStep2MaxRows32 = 32;  // tallest chunk of the binary32 kernel
 constexpr int kStep2MinRows = 8;
+// chunk heights a batch may take (chosen per size class by the autotuner)
+constexpr int kBatch2RowChoices[] = {32, 24, 16, 12, 8};
 #ifndef LTNE_STEP2_TARGET_WAVES
 #define LTNE_STEP2_TARGET_WAVES 16384
 #endif
@@ -76,14 +82,17 @@ __host__ __device__ constexpr int step2_out(int periodic_x) { return 63 - step2_
 __host__ __device__ constexpr int step2_waves(int nx, int ny, int periodic_x, int rows) {
   return ((nx + step2_out(periodic_x) - 1) / step2_out(periodic_x)) * ((ny + rows - 1) / rows);
 }
-// Chunk height of a single lattice's two-step launches.
-inline int step2_rows(int nx, int ny, int periodic_x) {
+// Chunk height of a single lattice's two-step launches (elem_bytes: 4 or 8,
+// the storage type).
+inline int step2_rows(int nx, int ny, int periodic_x, size_t elem_bytes) {
 #ifdef LTNE_STEP2_ROWS
-  (void)nx, (void)ny, (void)periodic_x;
+  (void)nx, (void)ny, (void)periodic_x, (void)elem_bytes;
   return LTNE_STEP2_ROWS;
 #else
+  const bool wide = elem_bytes == 8;
+  const int target = wide ? kStep2TargetWaves / 2 : kStep2TargetWaves;
   for (int r : kStep2RowChoices)
-    if (step2_waves(nx, ny, periodic_x, r) >= kStep2TargetWaves) return r;
+    if ((wide || r <= kStep2MaxRows32) && step2_waves(nx, ny, periodic_x, r) >= target) return r;
   return kStep2MinRows;
 #endif
 }

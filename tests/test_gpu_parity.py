@@ -299,7 +299,7 @@ TWO_STEP_CASES = [
     ("cavity 1024x1024, both extensions", lambda: (I.cavity_small(nx=1024, ny=1024, precision=I.FP32, Ra=1e5,
                                                                   thermal_correction=1, pore_size=0.0135),
                                                    None, None, None)),
-    # lattices that take taller chunks (the tallest of 32, 24, 16, 12 rows
+    # lattices that take taller chunks (FP32: the tallest of 32, 24, 16, 12 rows
     # giving 16384 wavefronts): 12 rows with x walls (66 strips x 251
     # chunks), 24 rows periodic (97 x 209) and the 8192^2 layer, 32 rows
     # (133 x 256), ragged last chunks in the first two
@@ -315,7 +315,11 @@ TWO_STEP_CASES = [
     ("fp64 cavity 1024x1024, both extensions", lambda: (I.cavity_small(nx=1024, ny=1024, Ra=1e5,
                                                                        thermal_correction=1, pore_size=0.0135),
                                                         None, None, None)),
+    # 64-row chunks (the binary64 kernel's tallest, taken from 8192
+    # wavefronts on): the full layer (133 strips x 128 chunks) and a walled
+    # cavity with a ragged last chunk of 4 rows (135 x 65)
     ("fp64 layer 8192x8192, tall chunks", lambda: I.throughput(n=8192, precision=I.FP64)),
+    ("fp64 cavity 8200x4100, tall chunks", lambda: (I.cavity_small(nx=8200, ny=4100, Ra=1e6), None, None, None)),
 ]
 
 
