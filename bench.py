@@ -277,18 +277,36 @@ def copy_bandwidth(gib: float = 1.0, reps: int = 5):
     return {"bytes_read": n * 4, "bytes_written": n * 4, "ms": ms, "gbs": 2 * n * 4 / ms / 1e6}
 
 
-def is_head_kernel(name: str) -> bool:
-    """The FP32 two-step kernel with the porosity field (the 8192^2 layer's),
-    by its demangled or mangled name in a rocprofv3 record."""
-    return "step2_kernel<float, 1>" in name or "step2_kernelIfLi1E" in name
+# element type of each two-step form's kernel, as rocprofv3 names it
+TWO_STEP_TYPE = {"f32": "float", "f64": "double"}
 
 
-def ingest_counters(fetch_csv: str, write_csv: str, copy_bytes: int, out_path: str):
+def is_two_step_kernel(name: str, tag: str = "f32") -> bool:
+    """The two-step kernel of form `tag` with the porosity field (the 8192^2
+    layer's), by its demangled or mangled name in a rocprofv3 record."""
+    t = TWO_STEP_TYPE[tag]
+    return ("step2_kernel<%s, 1>" % t) in name or ("step2_kernelI%sLi1E" % t[0]) in name
+
+
+def _merge_record(out_path: str, tag: str, rec: dict):
+    """Writes rec as entry `tag` of a counter summary, keeping the others."""
+    try:
+        with open(out_path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        t = {}
+    t[tag] = rec
+    with open(out_path, "w") as f:
+        json.dump(t, f, indent=1)
+    print(json.dumps({tag: rec}, indent=1))
+
+
+def ingest_counters(fetch_csv: str, write_csv: str, copy_bytes: int, out_path: str, tag: str = "f32"):
     """Turns two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per
-    dispatch) of `bench.py --forms f32 --copy-check` into HBM bytes per
-    launch of the FP32 two-step kernel (two node updates per node), each
-    scaled by the same counter's reading on the plain copy of copy_bytes read
-    and copy_bytes written."""
+    dispatch) of `bench.py --forms <tag>` into HBM bytes per launch of that
+    form's two-step kernel (two node updates per node), each scaled by the
+    same counter's reading on the plain copy of copy_bytes read and
+    copy_bytes written that bench.py times in the same run."""
     import csv
 
     def per_kernel(path, counter):
@@ -305,40 +323,35 @@ def ingest_counters(fetch_csv: str, write_csv: str, copy_bytes: int, out_path: s
         vals = per_kernel(path, counter)
         copy = [v for k, vs in vals.items() if "copy" in k.lower()
                 for v in vs if v * 1024 > 0.25 * copy_bytes]
-        step = [v for k, vs in vals.items() if is_head_kernel(k) for v in vs]
+        step = [v for k, vs in vals.items() if is_two_step_kernel(k, tag) for v in vs]
         if not copy or not step:
             raise SystemExit("counters for the copy or the step kernel not found in %s" % path)
         scale = copy_bytes / (np.median(copy) * 1024.0)
         out[counter] = {"step_kib_median": float(np.median(step)), "copy_kib_median": float(np.median(copy)),
                         "scale": float(scale), "step_bytes": float(np.median(step) * 1024.0 * scale)}
     total = out["FETCH_SIZE"]["step_bytes"] + out["WRITE_SIZE"]["step_bytes"]
-    rec = {"f32": {"kernel_hash": kernel_hash(), "bytes_per_launch": total,
-                   "must_move_bytes_per_launch": BYTES_PER_LUP["f32"] * N * N,
-                   "one_step_equivalent_bytes_per_launch": BYTES_PER_LUP["f32"] * N * N * 2,
-                   "counters": out}}
-    with open(out_path, "w") as f:
-        json.dump(rec, f, indent=1)
-    print(json.dumps(rec, indent=1))
+    _merge_record(out_path, tag, {"kernel_hash": kernel_hash(), "bytes_per_launch": total,
+                                  "must_move_bytes_per_launch": BYTES_PER_LUP[tag] * N * N,
+                                  "one_step_equivalent_bytes_per_launch": BYTES_PER_LUP[tag] * N * N * 2,
+                                  "counters": out})
 
 
-def ingest_sq(csv_path: str, out_path: str):
+def ingest_sq(csv_path: str, out_path: str, tag: str = "f32"):
     """Turns a rocprofv3 --pmc run with SQ_INSTS_VALU (and SQ_WAVES) of
-    `bench.py --forms f32` into wavefront vector instructions per launch of
-    the FP32 two-step kernel (median over its dispatches)."""
+    `bench.py --forms <tag>` into wavefront vector instructions per launch of
+    that form's two-step kernel (median over its dispatches)."""
     import csv
     vals = {}
     for row in csv.DictReader(open(csv_path)):
         k = row["Kernel_Name"]
-        if is_head_kernel(k):
+        if is_two_step_kernel(k, tag):
             vals.setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
     if "SQ_INSTS_VALU" not in vals:
         raise SystemExit("SQ_INSTS_VALU of the two-step kernel not found in %s" % csv_path)
-    rec = {"f32": {"kernel_hash": kernel_hash(), "valu_per_launch": float(np.median(vals["SQ_INSTS_VALU"])),
-                   "counters": {k: float(np.median(v)) for k, v in vals.items()},
-                   "dispatches": len(vals["SQ_INSTS_VALU"])}}
-    with open(out_path, "w") as f:
-        json.dump(rec, f, indent=1)
-    print(json.dumps(rec, indent=1))
+    _merge_record(out_path, tag, {"kernel_hash": kernel_hash(),
+                                  "valu_per_launch": float(np.median(vals["SQ_INSTS_VALU"])),
+                                  "counters": {k: float(np.median(v)) for k, v in vals.items()},
+                                  "dispatches": len(vals["SQ_INSTS_VALU"])})
 
 
 def clock_probe(forms=("f32", "f16s", "f64"), samples: int = 6, interval_s: float = 0.4):
@@ -511,6 +524,22 @@ def time_extras():
     return out
 
 
+def counter_figures(tag: str, r: dict) -> dict:
+    """HBM traffic and vector-issue fractions of a two-step form's launch from
+    its committed counter runs (only those taken on the current sources)."""
+    out = {}
+    launch_s = r["launch_ms"] * 1e-3
+    traffic = measured_traffic(tag)
+    if traffic:
+        out["traffic_bytes_per_launch"] = traffic
+        out["traffic_frac"] = round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)
+    valu = measured_valu(tag)
+    if valu:
+        out["valu_per_node_update"] = round(valu * 64 / (2 * N * N), 1)
+        out["valu_issue_frac"] = round(valu / VALU_ISSUE_PER_S / launch_s, 4)
+    return out
+
+
 def roofline(head: str, r: dict, traffic):
     """Roofline of the dominant kernel.  achieved = the HBM bytes one launch
     must move (per node: every population read once and written once in the
@@ -576,13 +605,15 @@ def main():
                     help="convert rocprofv3 FETCH_SIZE / WRITE_SIZE runs into profiles/traffic.json")
     ap.add_argument("--ingest-sq", metavar="SQ_CSV",
                     help="convert a rocprofv3 SQ_INSTS_VALU run into profiles/sq.json")
+    ap.add_argument("--counters-form", default="f32", choices=sorted(TWO_STEP_TYPE),
+                    help="the two-step form whose kernel the ingested counter runs measured")
     args = ap.parse_args()
     if args.ingest_counters:
         ingest_counters(args.ingest_counters[0], args.ingest_counters[1], 2 ** 30,
-                        os.path.join(ROOT, "profiles", "traffic.json"))
+                        os.path.join(ROOT, "profiles", "traffic.json"), args.counters_form)
         return
     if args.ingest_sq:
-        ingest_sq(args.ingest_sq, os.path.join(ROOT, "profiles", "sq.json"))
+        ingest_sq(args.ingest_sq, os.path.join(ROOT, "profiles", "sq.json"), args.counters_form)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -661,8 +692,8 @@ def main():
         "cpu_baseline": cpu,
         "copy_reference": copy,
         "extras": extras,
-        "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
-                         for kk, vv in v.items()} for k, v in res.items()},
+        "variants": {k: dict({kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                              for kk, vv in v.items()}, **counter_figures(k, v)) for k, v in res.items()},
         "batch256_f32": batch,
         "adjoint": adjoint,
     }

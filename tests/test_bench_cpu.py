@@ -127,3 +127,31 @@ def test_sq_ingest_and_roofline_block(tmp_path, monkeypatch):
     assert abs(out["traffic_gbs"] - 11.0e9 / 2.5e-3 / 1e9) < 0.1
     single = bench.roofline("f64", {"launch_ms": 3.6, "steps_per_launch": 1}, None)
     assert single["bytes_per_launch"] == 312 * n and "valu_issue" not in single
+
+
+def test_counter_runs_of_both_two_step_forms(tmp_path, monkeypatch, capsys):
+    """Counter runs of the FP32 and the FP64 two-step kernels land in one
+    summary, each under its form, picked out by the kernel's element type;
+    the bench line's per-form figures then divide them by the launch time."""
+    _copy_sources(tmp_path)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    out = tmp_path / "profiles" / "traffic.json"
+    copy = "__amd_rocclr_copyBuffer"
+    f32k = "void ltne::step2_kernel<float, 1>(float const*, ...)"
+    f64k = "void ltne::step2_kernel<double, 1>(double const*, ...)"
+    gib = 2 ** 30
+    _counter_csv(tmp_path / "f.csv", "FETCH_SIZE", [(copy, gib / 2048), (f32k, 1.0e6), (f64k, 5.0e6)])
+    _counter_csv(tmp_path / "w.csv", "WRITE_SIZE", [(copy, gib / 1024), (f32k, 2.0e6), (f64k, 7.0e6)])
+    bench.ingest_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), gib, str(out), "f32")
+    bench.ingest_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), gib, str(out), "f64")
+    capsys.readouterr()
+    t = json.loads(out.read_text())
+    assert t["f32"]["bytes_per_launch"] == pytest.approx(1.0e6 * 2048 + 2.0e6 * 1024)
+    assert t["f64"]["bytes_per_launch"] == pytest.approx(5.0e6 * 2048 + 7.0e6 * 1024)
+    assert t["f64"]["must_move_bytes_per_launch"] == 312 * 8192 * 8192
+    fig = bench.counter_figures("f64", {"launch_ms": 5.0})
+    assert fig["traffic_bytes_per_launch"] == t["f64"]["bytes_per_launch"]
+    assert abs(fig["traffic_frac"] - t["f64"]["bytes_per_launch"] / 5e-3 / 1e9 / 8000.0) < 1e-4
+    assert "valu_issue_frac" not in fig
+    assert bench.counter_figures("f16s", {"launch_ms": 1.0}) == {}
