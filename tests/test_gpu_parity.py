@@ -346,6 +346,29 @@ def test_two_step_launch_equals_single_steps(B, case, nsteps):
     say("two-step launches equal single steps bit for bit:", name, nsteps, "steps")
 
 
+def test_fp64_pairs_match_oracle(B, oracle):
+    """The FP64 form's two-step launches against the oracle directly (the
+    bit-for-bit cases above tie them to single steps): a walled 1038 x 1030
+    cavity (18 strips x 129 chunks of 8 rows) with smoothed porosity and H_v
+    fields, initial temperature fields and a body acceleration (velocities
+    of 1e-3, which binary64 resolves to 1e-12: a cavity heated only from a
+    wall moves at 1e-4 after 200 steps, below that resolution, see the
+    strips), 200 steps in pairs, the last pair writing the macros; whole
+    field at 1e-12, and the mass and energy sums."""
+    say("fp64 pairs 1038x1030 cavity with fields, 200 steps, against the oracle")
+    nx, ny = 1038, 1030
+    z1 = I.smoothed_noise(21, ny, nx, sigma=8.0)
+    z2 = I.smoothed_noise(22, ny, nx, sigma=8.0)
+    p = I.complete(nx=nx, ny=ny, Ra=1e5, body_force=(2e-5, -1e-5), T_wall=(1.0, 0.0, 0.0, 0.0))
+    phi = np.clip(0.6 + 0.1 * z1, 0.35, 0.9)
+    Hv = 10.0 * (1 + 0.3 * np.clip(z2, -1, 1))
+    g, o = pair(B, oracle, p, 200, phi=phi, Hv=Hv, Tf0=0.5 + 0.1 * z2, Ts0=0.5 - 0.1 * z1)
+    compare(g.macros(), o.macros(), 1e-12, GATED, "fp64 pairs cavity 1038x1030")
+    gd, od = g.diagnostics(), o.diagnostics()
+    for a, b in zip(gd[:2], od[:2]):
+        assert abs(a - b) <= 1e-12 * abs(b), (a, b)
+
+
 RECORDED_CASES = [
     ("fp64 64x64", lambda: (I.cavity_small(), None, None)),
     ("fp32 96x80 phi field", lambda: (I.cavity_small(nx=96, ny=80, precision=I.FP32, Ra=3e4),
