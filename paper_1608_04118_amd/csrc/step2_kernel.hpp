@@ -1,7 +1,8 @@
 // Two fused time steps per launch for the FP32 form (binary32 storage,
-// binary32 flow and binary64 temperature arithmetic).  The single-step kernel
-// is bound by memory traffic; computing two steps per pass over the
-// populations halves the traffic per lattice-node update.
+// binary32 flow and binary64 temperature arithmetic) and the FP64 form (the
+// same code over binary64 populations).  The single-step kernel is bound by
+// memory traffic; computing two steps per pass over the populations halves
+// the traffic per lattice-node update.
 //
 // Each wavefront owns a strip of columns and a chunk of rows and marches
 // down the rows.  Lane l holds column x0 - H + l (H = 1 on a periodic x axis,
@@ -15,8 +16,8 @@
 // The lanes at the strip edges only feed their neighbours.  A wall row takes
 // the pulls of its inward neighbour row (non-equilibrium extrapolation), so
 // it is updated at that row's step.  The results equal two single steps bit
-// for bit: the same node update, and binary32 values in registers instead of
-// a binary32 round trip through memory.
+// for bit: the same node update, and values of the storage type in
+// registers instead of a round trip through memory.
 #pragma once
 
 #include "step_kernel.hpp"
