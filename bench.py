@@ -616,7 +616,7 @@ def main():
         ingest_sq(args.ingest_sq, os.path.join(ROOT, "profiles", "sq.json"), args.counters_form)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the step would shard as horizontal slabs with a halo exchange per step); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)

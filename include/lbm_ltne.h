@@ -54,7 +54,7 @@ extern "C" {
 #define LBM_ENOMEM (-2)       /* device allocation failed or caller pool too small */
 #define LBM_EHIP (-3)         /* a HIP runtime call failed (message in last_error) */
 #define LBM_EDIVERGED (-4)    /* non-finite mass or energy detected (diagnostics, or the check of diag_every) */
-#define LBM_EUNSUPPORTED (-5) /* valid request this build does not implement */
+#define LBM_EUNSUPPORTED (-5) /* valid request the library does not implement */
 #define LBM_ENODEV (-6)       /* no gfx950 device is available */
 
 /* Storage / arithmetic forms. */
