@@ -477,9 +477,11 @@ int lbm_ltne_step(lbm_ltne_t h, int64_t nsteps) {
   // two steps per launch where the lattice gives the two-step kernel enough
   // wavefronts to hide its latency (each wavefront runs a serial chain of
   // rows); small lattices run faster one step at a time
-  const bool pairs = (h->p.precision == LBM_FP32 || h->p.precision == LBM_FP64) &&
+  const bool fp64 = h->p.precision == LBM_FP64;
+  const bool pairs = (h->p.precision == LBM_FP32 || fp64) &&
                      step2_addressable(h->p.nx, storage_bytes(h->p.precision)) &&
-                     step2_waves(h->p.nx, h->p.ny, h->p.periodic_x, kStep2MinRows) >= LTNE_STEP2_MIN_WAVES;
+                     step2_waves(h->p.nx, h->p.ny, h->p.periodic_x, kStep2MinRows) >=
+                         (fp64 ? LTNE_STEP2_MIN_WAVES_64 : LTNE_STEP2_MIN_WAVES);
   const int64_t de = h->p.diag_every;
   auto checked = [de](int64_t t) { return de > 0 && t % de == 0; };
   void* scratch_mac = h->mac(1 - h->mcur);  // overwritten by the call's last step

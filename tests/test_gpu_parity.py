@@ -307,12 +307,14 @@ TWO_STEP_CASES = [
                                                 None, None, None)),
     ("layer 6000x5000, tall chunks", lambda: I.throughput(n=6000, ny=5000)),
     ("layer 8192x8192, tall chunks", lambda: I.throughput(n=8192)),
-    # the FP64 form
-    ("fp64 layer 1100x1027, phi field", lambda: I.throughput(n=1100, ny=1027, precision=I.FP64)),
-    ("fp64 cavity 1038x1030", lambda: (I.cavity_small(nx=1038, ny=1030, Ra=1e5), None, None, None)),
-    ("fp64 torus 1030x1030", lambda: (I.complete(nx=1030, ny=1030, periodic_x=1, periodic_y=1, precision=I.FP64,
+    # the FP64 form (pairs from 4096 wavefronts of 8 rows on): 27 strips x
+    # 191 chunks with a ragged last chunk, x walls at a strip start
+    # (1648 = 27 x 61 + 1), periodic wraps on both axes
+    ("fp64 layer 1650x1527, phi field", lambda: I.throughput(n=1650, ny=1527, precision=I.FP64)),
+    ("fp64 cavity 1648x1630", lambda: (I.cavity_small(nx=1648, ny=1630, Ra=1e5), None, None, None)),
+    ("fp64 torus 1600x1600", lambda: (I.complete(nx=1600, ny=1600, periodic_x=1, periodic_y=1, precision=I.FP64,
                                                  Ra=1e4, body_force=(1e-4, -2e-5)), None, None, None)),
-    ("fp64 cavity 1024x1024, both extensions", lambda: (I.cavity_small(nx=1024, ny=1024, Ra=1e5,
+    ("fp64 cavity 1600x1600, both extensions", lambda: (I.cavity_small(nx=1600, ny=1600, Ra=1e5,
                                                                        thermal_correction=1, pore_size=0.0135),
                                                         None, None, None)),
     # 64-row chunks (the binary64 kernel's tallest, taken from 8192
@@ -348,22 +350,22 @@ def test_two_step_launch_equals_single_steps(B, case, nsteps):
 
 def test_fp64_pairs_match_oracle(B, oracle):
     """The FP64 form's two-step launches against the oracle directly (the
-    bit-for-bit cases above tie them to single steps): a walled 1038 x 1030
-    cavity (18 strips x 129 chunks of 8 rows) with smoothed porosity and H_v
+    bit-for-bit cases above tie them to single steps): a walled 1648 x 1630
+    cavity (28 strips x 204 chunks of 8 rows) with smoothed porosity and H_v
     fields, initial temperature fields and a body acceleration (velocities
     of 1e-3, which binary64 resolves to 1e-12: a cavity heated only from a
     wall moves at 1e-4 after 200 steps, below that resolution, see the
     strips), 200 steps in pairs, the last pair writing the macros; whole
     field at 1e-12, and the mass and energy sums."""
-    say("fp64 pairs 1038x1030 cavity with fields, 200 steps, against the oracle")
-    nx, ny = 1038, 1030
+    say("fp64 pairs 1648x1630 cavity with fields, 200 steps, against the oracle")
+    nx, ny = 1648, 1630
     z1 = I.smoothed_noise(21, ny, nx, sigma=8.0)
     z2 = I.smoothed_noise(22, ny, nx, sigma=8.0)
     p = I.complete(nx=nx, ny=ny, Ra=1e5, body_force=(2e-5, -1e-5), T_wall=(1.0, 0.0, 0.0, 0.0))
     phi = np.clip(0.6 + 0.1 * z1, 0.35, 0.9)
     Hv = 10.0 * (1 + 0.3 * np.clip(z2, -1, 1))
     g, o = pair(B, oracle, p, 200, phi=phi, Hv=Hv, Tf0=0.5 + 0.1 * z2, Ts0=0.5 - 0.1 * z1)
-    compare(g.macros(), o.macros(), 1e-12, GATED, "fp64 pairs cavity 1038x1030")
+    compare(g.macros(), o.macros(), 1e-12, GATED, "fp64 pairs cavity 1648x1630")
     gd, od = g.diagnostics(), o.diagnostics()
     for a, b in zip(gd[:2], od[:2]):
         assert abs(a - b) <= 1e-12 * abs(b), (a, b)
