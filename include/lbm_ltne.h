@@ -182,7 +182,7 @@ int lbm_ltne_create(const lbm_ltne_params *p, const double *phi_field, const dou
 /* Advances nsteps >= 0 time steps (asynchronous).  Each step is one fused
  * launch: pull streaming, wall reconstruction, macros, the three collisions,
  * store.  In the FP32 and FP64 forms, on lattices that yield at least 1024
- * (FP32) or 4096 (FP64) strips of 62 (periodic x) or 61 columns by 8 rows,
+ * (FP32) or 2560 (FP64) strips of 62 (periodic x) or 61 columns by 8 rows,
  * the steps of a call advance in pairs, two steps per launch with the
  * intermediate time level kept on chip (an odd last step, and the steps
  * checked under diag_every, alone); the result equals single steps bit for

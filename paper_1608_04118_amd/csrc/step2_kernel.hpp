@@ -71,14 +71,15 @@ static_assert(kBatch2Block % 64 == 0 && kBatch2Block <= 1024, "whole wavefronts 
 constexpr bool kStep2NtStore = LTNE_STEP2_NT_STORE != 0;
 // Two-step launches need this many wavefronts at the smallest chunk height
 // to hide the serial chain of rows each one runs; with fewer, single steps
-// are faster (512^2: 576).  The binary64 kernel runs one wavefront per SIMD
-// and needs four times as many (the FP64 layer: 1024^2 with 2176 wavefronts
-// 2% slower in pairs, 1536^2 with 4800 wavefronts 20% faster).
+// are faster (the FP32 layer: 640^2 with 880 wavefronts 2% slower in pairs,
+// 768^2 with 1248 2% faster).  The binary64 kernel runs one wavefront per
+// SIMD and needs more (the FP64 layer: 1024^2 with 2176 wavefronts 2% slower
+// in pairs, 1152^2 with 2736 13% faster).
 #ifndef LTNE_STEP2_MIN_WAVES
 #define LTNE_STEP2_MIN_WAVES 1024
 #endif
 #ifndef LTNE_STEP2_MIN_WAVES_64
-#define LTNE_STEP2_MIN_WAVES_64 4096
+#define LTNE_STEP2_MIN_WAVES_64 2560
 #endif
 
 // Lanes left of a strip's first output column: one on a periodic x axis,

@@ -307,7 +307,7 @@ TWO_STEP_CASES = [
                                                 None, None, None)),
     ("layer 6000x5000, tall chunks", lambda: I.throughput(n=6000, ny=5000)),
     ("layer 8192x8192, tall chunks", lambda: I.throughput(n=8192)),
-    # the FP64 form (pairs from 4096 wavefronts of 8 rows on): 27 strips x
+    # the FP64 form (pairs from 2560 wavefronts of 8 rows on): 27 strips x
     # 191 chunks with a ragged last chunk, x walls at a strip start
     # (1648 = 27 x 61 + 1), periodic wraps on both axes
     ("fp64 layer 1650x1527, phi field", lambda: I.throughput(n=1650, ny=1527, precision=I.FP64)),
